@@ -1,0 +1,188 @@
+/*
+ * coex.h — C ABI of libcoex, a chunked speculative finite-automaton scan of
+ * DNA sequences on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Memeti & Pllana, "Analyzing large-scale DNA Sequences
+ * on Multi-core Architectures" (CSE 2015):
+ *   - the problem (Section II): text T[1..n] over {A,C,G,T}, a pattern set;
+ *     find every occurrence, overlapping ones included;
+ *   - the automaton (Section II): (Q, Sigma, delta, q0, F) with a complete
+ *     transition table, built by Aho-Corasick with the failure links folded
+ *     into explicit transitions (Section III.B.1, Fig. 2), or from a regular
+ *     expression (Table IV syntax);
+ *   - the scan (Section III, Algorithm 1): the text is cut into chunks; every
+ *     chunk is scanned speculatively from its possible starting states, the
+ *     redundant runs stop at the converging point, and a join links each
+ *     chunk's last state to the next chunk's first state; the counts are fixed
+ *     up at the converging point.  Results equal one sequential scan from q0.
+ *
+ * Conventions shared by every call
+ *   - Every call returns an int status: COEX_OK (0) or a negative COEX_E*
+ *     code; coex_strerror() names it.  No exception crosses the ABI.  On an
+ *     error, output buffers are left untouched unless stated otherwise.
+ *   - Handles (coex_dfa*) are created by the coex_compile_* / from_table calls,
+ *     are immutable afterwards, may be shared between threads, and are
+ *     released by coex_dfa_free().  The library keeps a device copy of the
+ *     tables per GPU, made on first use and freed with the handle.
+ *   - Sequence and result pointers named *_dev are device pointers (HIP
+ *     memory on the current device) owned by the caller; the library never
+ *     frees them.  Other pointers are host pointers.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     queued on it asynchronously unless the call says it synchronises.
+ *     Calls on the same stream may reuse one library workspace; calls that
+ *     run concurrently must use different streams.
+ *   - Alphabet: A,C,G,T in either case.  In a sequence every other byte (N,
+ *     IUPAC codes, newlines, ...) resets the automaton to q0, so no match ends
+ *     on or spans such a byte.  Patterns must be non-empty over A,C,G,T.
+ *   - Match end positions are 0-based indices of the last base of the match,
+ *     reported in ascending order, ties by ascending pattern id.
+ */
+#ifndef COEX_H
+#define COEX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define COEX_OK 0
+#define COEX_EINVAL (-1)      /* bad argument (NULL where not allowed, bad sizes, misaligned pointer) */
+#define COEX_EALPHABET (-2)   /* pattern character outside A,C,G,T, or an empty pattern */
+#define COEX_ETOOBIG (-3)     /* the automaton has more states than the device tables can index (4096) */
+#define COEX_ENOMEM (-4)      /* host or device allocation failed */
+#define COEX_ECAPACITY (-5)   /* result buffer too small; the required size is reported */
+#define COEX_EDEVICE (-6)     /* a HIP runtime call failed */
+#define COEX_EUNSUPPORTED (-7)/* option combination not supported */
+#define COEX_ESYNTAX (-8)     /* regular expression syntax error, or it matches the empty string */
+#define COEX_EINTERNAL (-9)   /* a device-side consistency check failed */
+
+/* ------------------------------------------------------- sequence formats */
+#define COEX_ENC_BYTE 0  /* one ASCII byte per base */
+#define COEX_ENC_2BIT 1  /* A=0 C=1 G=2 T=3, base i in bits 2*(i%4).. of byte i/4;
+                            N mask: bit i%8 of byte i/8 set = base i is N (its code is ignored) */
+
+typedef struct coex_dfa coex_dfa;
+
+/* A sequence resident in device memory.  `bases` (and `n_mask`) must be
+   16-byte aligned.  n_mask may be NULL for COEX_ENC_2BIT (no N) and is
+   ignored for COEX_ENC_BYTE. */
+typedef struct {
+  const void* bases;
+  const uint8_t* n_mask;
+  uint64_t n_bases;
+  int32_t encoding;
+} coex_seq;
+
+/* Scan options; 0 in any field lets the planner choose.
+   chunk:    bases per chunk (any value >= 1; the planner uses multiples of 512)
+   width:    lanes given to one chunk's speculative runs (1..64, power of two);
+             a chunk with more possible starting states than `width` is run
+             from all of them to its end instead
+   lookback: k, the number of bases before a chunk used to narrow its possible
+             starting states (1 = the paper's single last symbol; 1..8)
+   step:     symbols per table lookup in the main loop (1 or 2; 2 needs at
+             most 1024 states)
+   flags:    COEX_FLAG_CHECK: synchronise the stream at the end of the call and
+             return COEX_EINTERNAL if a device-side consistency check failed */
+typedef struct {
+  uint32_t chunk;
+  uint32_t width;
+  uint32_t lookback;
+  uint32_t step;
+  uint32_t flags;
+} coex_opts;
+
+#define COEX_FLAG_CHECK 1u
+
+/* Facts about a compiled automaton. */
+typedef struct {
+  uint32_t n_states;    /* |Q| */
+  uint32_t n_patterns;  /* number of pattern ids (counts arrays have this length) */
+  uint32_t n_accepting; /* |F| */
+  uint32_t q0;          /* start state */
+  uint32_t sync_depth;  /* smallest d such that any two states reach the same state after any d
+                           symbols; 0xFFFFFFFF if no such d exists */
+  uint32_t max_out;     /* largest number of patterns ended by one state */
+  uint32_t max_pss[9];  /* max_pss[k] = largest number of possible starting states after a
+                           k-base lookback (k = 1..8); max_pss[0] = n_states */
+} coex_dfa_info_t;
+
+/* ------------------------------------------------------------ automata */
+
+/* Aho-Corasick automaton of `n` patterns (Section II; failure links folded
+   into a complete table, Section III.B.1).  Pattern id = index in `kmers`.
+   Duplicates are allowed and each id counts every occurrence.  Patterns may
+   have different lengths.  Errors: EINVAL (n == 0 or NULL), EALPHABET,
+   ETOOBIG, ENOMEM. */
+int coex_compile_kmers(const char* const* kmers, uint32_t n, coex_dfa** out);
+
+/* Search automaton of one regular expression R (Table IV syntax): alternation
+   '|', grouping '()', classes '[ACG]', '.', and the repeats '?', '*', '+',
+   '{m}', '{m,}', '{m,n}'.  The automaton recognises Sigma* R and is minimised;
+   it has one pattern (id 0), reported once per end position at which some
+   match of R ends.  Errors: EINVAL, ESYNTAX (also for an R that matches the
+   empty string), ETOOBIG, ENOMEM. */
+int coex_compile_regex(const char* regex, coex_dfa** out);
+
+/* An automaton given as a table (Section II quintuple): delta[s*4 + c] is the
+   successor of state s on symbol c (A,C,G,T = 0..3); out_offsets[s] ..
+   out_offsets[s+1] index into out_ids the pattern ids that end at state s
+   (a state with an empty set is not final).  Host arrays, copied.  State
+   numbering is kept in every output.  Errors: EINVAL (a successor or id out
+   of range, offsets not non-decreasing, a repeated id within a state),
+   ETOOBIG, ENOMEM. */
+int coex_dfa_from_table(const uint32_t* delta, uint32_t n_states, uint32_t q0, const uint32_t* out_offsets,
+                        const uint32_t* out_ids, uint32_t n_patterns, coex_dfa** out);
+
+int coex_dfa_info(const coex_dfa* dfa, coex_dfa_info_t* info);
+
+/* Copies the automaton out as plain host arrays: delta[n_states*4],
+   out_offsets[n_states+1], out_ids[out_offsets[n_states]] (ascending within a
+   state).  Any pointer may be NULL to skip that array. */
+int coex_dfa_export(const coex_dfa* dfa, uint32_t* delta, uint32_t* out_offsets, uint32_t* out_ids);
+
+void coex_dfa_free(coex_dfa* dfa);
+
+/* ------------------------------------------------------------ scans */
+
+/* Per-pattern match counts of `dfa` over `seq` (Section III, Algorithm 1:
+   chunks, possible starting states, converging point, join, fix-up).
+   counts_dev: uint64[n_patterns] device buffer, overwritten.
+   Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int coex_count(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, const coex_opts* opts,
+               void* stream);
+
+/* End positions of every match ("count and extract", Section III.A):
+   pos_dev int64[capacity] and pattern_dev uint32[capacity] (may be NULL)
+   receive the matches in ascending end position, ties by pattern id.
+   *n_found (host) receives the number of matches.  Synchronises `stream`
+   once (to read the total).  If the total exceeds `capacity`, nothing is
+   written, *n_found holds the required size and ECAPACITY is returned. */
+int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
+              uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream);
+
+/* The per-chunk records of Algorithm 1 (CR: init state, last state, counts
+   per pattern) for the true starting state of each chunk, for chunks of
+   `chunk` bases (the last chunk takes the remainder).  n_chunks =
+   ceil(n_bases / chunk) (at least 1).  init_dev/last_dev: uint32[n_chunks];
+   counts_dev: uint64[n_chunks * n_patterns].  Asynchronous. */
+int coex_count_chunks(const coex_dfa* dfa, const coex_seq* seq, uint32_t chunk, uint32_t* init_dev,
+                      uint32_t* last_dev, uint64_t* counts_dev, void* stream);
+
+/* Counts for every (sequence, automaton) pair: counts_dev[s * n_dfa + d] =
+   total number of matches (all pattern ids) of dfas[d] in seqs[s].  All pairs
+   run in one persistent launch.  Asynchronous. */
+int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_seq* seqs, uint32_t n_seq,
+                       uint64_t* counts_dev, const coex_opts* opts, void* stream);
+
+const char* coex_strerror(int status);
+
+/* Version string of the library build. */
+const char* coex_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COEX_H */

@@ -1,0 +1,290 @@
+"""Python binding of libcoex (include/coex.h): the chunked speculative
+finite-automaton scan of DNA sequences on MI355X.
+
+Argument marshalling only: every step of the scan runs in the HIP kernels of
+``libcoex.so``.  PyTorch supplies device memory and streams.  If the shared
+library is missing, importing this package raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoex.so")
+
+ENC_BYTE = 0
+ENC_2BIT = 1
+FLAG_CHECK = 1
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -5: "ECAPACITY",
+          -6: "EDEVICE", -7: "EUNSUPPORTED", -8: "ESYNTAX", -9: "EINTERNAL"}
+
+EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
+            "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_find", "coex_count_chunks",
+            "coex_count_batched", "coex_strerror", "coex_version"]
+
+
+class CoexError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__("%s%s (%s)" % (what + ": " if what else "", _lib().coex_strerror(status).decode(),
+                                        self.name))
+
+
+class _Seq(ctypes.Structure):
+    _fields_ = [("bases", ctypes.c_void_p), ("n_mask", ctypes.c_void_p), ("n_bases", ctypes.c_uint64),
+                ("encoding", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint32), ("width", ctypes.c_uint32), ("lookback", ctypes.c_uint32),
+                ("step", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_uint32), ("n_patterns", ctypes.c_uint32), ("n_accepting", ctypes.c_uint32),
+                ("q0", ctypes.c_uint32), ("sync_depth", ctypes.c_uint32), ("max_out", ctypes.c_uint32),
+                ("max_pss", ctypes.c_uint32 * 9)]
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcoex.so is not built (run __graft_entry__.build() or "
+                              "python paper_1509_01506_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        p, u32, u64, ci = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        L.coex_compile_kmers.argtypes = [p, u32, p]
+        L.coex_compile_regex.argtypes = [ctypes.c_char_p, p]
+        L.coex_dfa_from_table.argtypes = [p, u32, u32, p, p, u32, p]
+        L.coex_dfa_info.argtypes = [p, p]
+        L.coex_dfa_export.argtypes = [p, p, p, p]
+        L.coex_dfa_free.argtypes = [p]
+        L.coex_dfa_free.restype = None
+        L.coex_count.argtypes = [p, p, p, p, p]
+        L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
+        L.coex_count_chunks.argtypes = [p, p, u32, p, p, p, p]
+        L.coex_count_batched.argtypes = [p, u32, p, u32, p, p, p]
+        L.coex_strerror.argtypes = [ci]
+        L.coex_strerror.restype = ctypes.c_char_p
+        L.coex_version.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("coex_dfa_free", "coex_strerror", "coex_version"):
+                getattr(L, name).restype = ci
+        _L = L
+    return _L
+
+
+_lib()  # fail loudly at import when the native library is absent
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise CoexError(rc, what)
+
+
+# ------------------------------------------------------------------ automata
+@dataclass
+class Info:
+    n_states: int
+    n_patterns: int
+    n_accepting: int
+    q0: int
+    sync_depth: Optional[int]
+    max_out: int
+    max_pss: list
+
+
+class Dfa:
+    """A compiled automaton (library handle)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @staticmethod
+    def kmers(kmers: Sequence[str]) -> "Dfa":
+        """Aho-Corasick automaton; pattern id = index."""
+        enc = [k.encode("ascii") for k in kmers]
+        arr = (ctypes.c_char_p * max(1, len(enc)))(*enc)
+        out = ctypes.c_void_p()
+        _check(_lib().coex_compile_kmers(ctypes.cast(arr, ctypes.c_void_p), len(enc), ctypes.byref(out)),
+               "compile_kmers")
+        return Dfa(out.value)
+
+    @staticmethod
+    def regex(text: str) -> "Dfa":
+        out = ctypes.c_void_p()
+        _check(_lib().coex_compile_regex(text.encode("ascii"), ctypes.byref(out)), "compile_regex")
+        return Dfa(out.value)
+
+    @staticmethod
+    def table(delta, q0: int, out_offsets, out_ids, n_patterns: int) -> "Dfa":
+        d = np.ascontiguousarray(delta, dtype=np.uint32)
+        o = np.ascontiguousarray(out_offsets, dtype=np.uint32)
+        i = np.ascontiguousarray(out_ids, dtype=np.uint32)
+        if i.size == 0:
+            i = np.zeros(1, dtype=np.uint32)
+        out = ctypes.c_void_p()
+        _check(_lib().coex_dfa_from_table(d.ctypes.data, d.size // 4, int(q0), o.ctypes.data, i.ctypes.data,
+                                          int(n_patterns), ctypes.byref(out)), "dfa_from_table")
+        return Dfa(out.value)
+
+    def info(self) -> Info:
+        x = _Info()
+        _check(_lib().coex_dfa_info(self._h, ctypes.byref(x)), "dfa_info")
+        return Info(x.n_states, x.n_patterns, x.n_accepting, x.q0,
+                    None if x.sync_depth == 0xFFFFFFFF else x.sync_depth, x.max_out, list(x.max_pss))
+
+    def export(self):
+        """(delta uint32[n*4], q0, out_offsets uint32[n+1], out_ids uint32[...])."""
+        inf = self.info()
+        d = np.zeros(inf.n_states * 4, dtype=np.uint32)
+        o = np.zeros(inf.n_states + 1, dtype=np.uint32)
+        _check(_lib().coex_dfa_export(self._h, d.ctypes.data, o.ctypes.data, None), "dfa_export")
+        i = np.zeros(max(1, int(o[-1])), dtype=np.uint32)
+        _check(_lib().coex_dfa_export(self._h, None, None, i.ctypes.data), "dfa_export")
+        return d, inf.q0, o, i[: int(o[-1])]
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib().coex_dfa_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ sequences
+@dataclass
+class DeviceSeq:
+    """A sequence in device memory (torch tensors keep the buffers alive)."""
+    bases: "object"           # torch.uint8 CUDA tensor
+    n: int
+    encoding: int = ENC_BYTE
+    nmask: "object" = None    # torch.uint8 CUDA tensor or None
+
+    def _c(self) -> _Seq:
+        return _Seq(self.bases.data_ptr() if self.n else 0,
+                    self.nmask.data_ptr() if self.nmask is not None else 0, self.n, self.encoding)
+
+
+def _pad16(arr: np.ndarray) -> np.ndarray:
+    n = arr.size
+    padded = np.zeros(((n + 127) // 128) * 128 or 128, dtype=np.uint8)
+    padded[:n] = arr
+    return padded
+
+
+def to_device(data: np.ndarray, n: Optional[int] = None, encoding: int = ENC_BYTE,
+              nmask: Optional[np.ndarray] = None, device: str = "cuda") -> DeviceSeq:
+    """Copies a host sequence to the GPU (buffers padded to 128 bytes)."""
+    import torch
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    if n is None:
+        n = data.size if encoding == ENC_BYTE else data.size * 4
+    b = torch.from_numpy(_pad16(data)).to(device)
+    m = torch.from_numpy(_pad16(np.ascontiguousarray(nmask, dtype=np.uint8))).to(device) if nmask is not None \
+        else None
+    return DeviceSeq(b, int(n), encoding, m)
+
+
+def _opts(chunk=0, width=0, lookback=0, step=0, check=False) -> _Opts:
+    return _Opts(chunk, width, lookback, step, FLAG_CHECK if check else 0)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ scans
+def count(dfa: Dfa, seq: DeviceSeq, out=None, chunk: int = 0, width: int = 0, lookback: int = 0, step: int = 0,
+          check: bool = False, stream=None):
+    """Per-pattern match counts as an int64 CUDA tensor (the device buffer holds uint64)."""
+    import torch
+    P = dfa.info().n_patterns
+    if out is None:
+        out = torch.empty(max(1, P), dtype=torch.int64, device=seq.bases.device)
+    s = seq._c()
+    o = _opts(chunk, width, lookback, step, check)
+    _check(_lib().coex_count(dfa.handle, ctypes.byref(s), out.data_ptr(), ctypes.byref(o), _stream(stream)),
+           "count")
+    return out[:P]
+
+
+def find(dfa: Dfa, seq: DeviceSeq, capacity: Optional[int] = None, chunk: int = 0, width: int = 0,
+         lookback: int = 0, step: int = 0, stream=None):
+    """(end positions int64, pattern ids int32) CUDA tensors, ascending."""
+    import torch
+    dev = seq.bases.device
+    s = seq._c()
+    o = _opts(chunk, width, lookback, step)
+    n_found = ctypes.c_uint64(0)
+    cap = 0 if capacity is None else int(capacity)
+    pos = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
+    pat = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    rc = _lib().coex_find(dfa.handle, ctypes.byref(s), pos.data_ptr(), pat.data_ptr(), cap, ctypes.byref(n_found),
+                          ctypes.byref(o), _stream(stream))
+    if rc == -5 and capacity is None:
+        cap = int(n_found.value)
+        pos = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
+        pat = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+        rc = _lib().coex_find(dfa.handle, ctypes.byref(s), pos.data_ptr(), pat.data_ptr(), cap,
+                              ctypes.byref(n_found), ctypes.byref(o), _stream(stream))
+    _check(rc, "find")
+    m = int(n_found.value)
+    return pos[:m], pat[:m]
+
+
+def count_chunks(dfa: Dfa, seq: DeviceSeq, chunk: int, stream=None):
+    """Per-chunk records (init state, last state, counts[P]) for the true start states."""
+    import torch
+    dev = seq.bases.device
+    inf = dfa.info()
+    nc = max(1, (seq.n + chunk - 1) // chunk)
+    init = torch.empty(nc, dtype=torch.int32, device=dev)
+    last = torch.empty(nc, dtype=torch.int32, device=dev)
+    cnt = torch.empty(nc * max(1, inf.n_patterns), dtype=torch.int64, device=dev)
+    s = seq._c()
+    _check(_lib().coex_count_chunks(dfa.handle, ctypes.byref(s), int(chunk), init.data_ptr(), last.data_ptr(),
+                                    cnt.data_ptr(), _stream(stream)), "count_chunks")
+    return init, last, cnt[: nc * inf.n_patterns].view(nc, inf.n_patterns)
+
+
+def count_batched(dfas: Sequence[Dfa], seqs: Sequence[DeviceSeq], out=None, chunk: int = 0, width: int = 0,
+                  lookback: int = 0, step: int = 0, stream=None):
+    """counts[s, d] = total matches of dfas[d] in seqs[s] (int64 CUDA tensor)."""
+    import torch
+    dev = seqs[0].bases.device
+    hs = (ctypes.c_void_p * len(dfas))(*[d.handle.value for d in dfas])
+    ss = (_Seq * len(seqs))(*[s._c() for s in seqs])
+    if out is None:
+        out = torch.empty((len(seqs), len(dfas)), dtype=torch.int64, device=dev)
+    o = _opts(chunk, width, lookback, step)
+    _check(_lib().coex_count_batched(ctypes.cast(hs, ctypes.c_void_p), len(dfas), ctypes.cast(ss, ctypes.c_void_p),
+                                     len(seqs), out.data_ptr(), ctypes.byref(o), _stream(stream)),
+           "count_batched")
+    return out
+
+
+def version() -> str:
+    return _lib().coex_version().decode()

@@ -1,0 +1,971 @@
+// libcoex: kernels, host runtime and the C ABI (include/coex.h).
+//
+// Pipeline of one scan (Section III of the paper, re-laid out for one MI355X):
+//   k_init       clears the small device counters;
+//   k_spec_tail  per tile of 64 chunks: possible starting states from the
+//                lookback table, lockstep speculative runs with ballot
+//                convergence (Algorithm 1's converging point), then one scan of
+//                the rest of each chunk from the converged state;
+//   k_nonconv    chunks that did not converge inside the window: every
+//                candidate runs to the chunk end (the paper's non-converged
+//                runs), giving the chunk's state map on its candidates;
+//   k_compose    the join: true first state of every chunk from its
+//                predecessor's last state (constant maps absorb the chain);
+//   k_fixup      recounts [chunk start, converging point) from the true first
+//                state and checks it reaches the converged state (count
+//                fix-up of Algorithm 1 in an equivalent form);
+//   k_finalize   visits per final state -> per-pattern counts.
+// Positions add an exclusive scan of per-chunk counts and a second pass per
+// chunk from its true first state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "coex.h"
+#include "dfa.hpp"
+#include "kernels.hpp"
+
+namespace coex {
+
+// ====================================================================== kernels
+constexpr int kScanBlock = 1024;
+
+__device__ __forceinline__ void copy_to_lds(char* dst, const void* src, uint32_t bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+__global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    *a.nc_count = 0;
+    *a.err = 0;
+    *a.total = 0;
+  }
+  for (uint32_t i = t; i < a.n_acc; i += gridDim.x * blockDim.x) a.visits[i] = 0;
+  if (counts)
+    for (uint32_t i = t; i < n_counts; i += gridDim.x * blockDim.x) counts[i] = 0;
+}
+
+// Candidate list of chunk c: either one exact state (chunk 0, a reset inside
+// the lookback window, or a window that reaches the sequence start) or the
+// PSS table entry of the k-gram before the chunk.
+template <int ENC, int SHIFT>
+__device__ __forceinline__ void chunk_header(const ScanArgs& a, const Tab& tb, uint64_t lo, uint32_t& m, uint32_t& cbase,
+                             uint32_t& exact, bool& is_exact) {
+  m = 1;
+  cbase = 0;
+  exact = tb.q0s;
+  is_exact = true;
+  if (lo == 0) return;
+  const uint64_t k = a.k;
+  const uint64_t kk = lo < k ? lo : k;
+  bool reset = false;
+  uint32_t idx = 0;
+  for (uint64_t i = 0; i < kk; ++i) {
+    int col = load_col<ENC>(a, lo - kk + i);
+    if (col < 0) reset = true;
+    else idx |= col_to_code<ENC>((uint32_t)col) << (2 * i);
+  }
+  if (reset || kk < k) {
+    uint32_t s = tb.q0s;
+    for (uint64_t i = 0; i < kk; ++i) {
+      int col = load_col<ENC>(a, lo - kk + i);
+      s = col < 0 ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (uint32_t)col) & 0xFFFFu);
+    }
+    exact = s;
+    return;
+  }
+  is_exact = false;
+  cbase = a.pss_off[idx];
+  m = a.pss_off[idx + 1] - cbase;
+}
+
+// The first SPEC_WIN symbols of [lo, hi): columns two bits per base (base i
+// at bits 2i of the 128-bit pair sy0:sy1) and a reset bit per base (rs).
+template <int ENC>
+__device__ __forceinline__ void stage_symbols(const ScanArgs& a, uint64_t lo, uint64_t hi, uint64_t& sy0, uint64_t& sy1,
+                              uint64_t& rs) {
+  uint32_t c[4] = {0, 0, 0, 0}, r[4] = {0, 0, 0, 0};
+  if ((lo & 15) == 0 && lo + SPEC_WIN <= hi) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) load_word<ENC>(a, lo + 16 * w, c[w], r[w]);
+  } else {
+    for (uint32_t i = 0; i < SPEC_WIN && lo + i < hi; ++i) {
+      const int col = load_col<ENC>(a, lo + i);
+      const uint32_t bit = col < 0 ? 0u : (uint32_t)col;
+      // i / 16 selects the word; written without indexing a register array
+      const uint32_t w = i >> 4, sh = 2 * (i & 15), rb = col < 0 ? 1u << (i & 15) : 0u;
+      c[0] |= w == 0 ? bit << sh : 0u;
+      c[1] |= w == 1 ? bit << sh : 0u;
+      c[2] |= w == 2 ? bit << sh : 0u;
+      c[3] |= w == 3 ? bit << sh : 0u;
+      r[0] |= w == 0 ? rb : 0u;
+      r[1] |= w == 1 ? rb : 0u;
+      r[2] |= w == 2 ? rb : 0u;
+      r[3] |= w == 3 ? rb : 0u;
+    }
+  }
+  sy0 = (uint64_t)c[0] | ((uint64_t)c[1] << 32);
+  sy1 = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
+  rs = (uint64_t)r[0] | ((uint64_t)r[1] << 16) | ((uint64_t)r[2] << 32) | ((uint64_t)r[3] << 48);
+}
+
+template <int ENC, int SHIFT, int STEP, class Sink>
+__device__ __forceinline__ void tile(const ScanArgs& a, const Tab& tb, uint64_t tile_id, Sink& sink_proto) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t c = tile_id * TILE + lane;
+  const bool valid = c < a.n_chunks;
+  const uint64_t lo = valid ? c * a.chunk : 0;
+  const uint64_t hi = valid ? (lo + a.chunk < a.n ? lo + a.chunk : a.n) : 0;
+
+  // ---- this lane's chunk: candidates and its first SPEC_WIN symbols
+  uint32_t m = 0, cbase = 0, exact = 0;
+  bool is_exact = false;
+  if (valid) chunk_header<ENC, SHIFT>(a, tb, lo, m, cbase, exact, is_exact);
+  uint64_t sy0 = 0, sy1 = 0, rs = 0;
+  if (valid) stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
+  const uint32_t len = (uint32_t)((hi - lo) < SPEC_WIN ? (hi - lo) : SPEC_WIN);
+
+  // ---- speculation: rounds of 64/G chunks, G lanes per chunk
+  const uint32_t G = a.group;
+  const uint32_t R = 64u / G;
+  const uint32_t gidx = lane / G, gi = lane % G, gl = lane & ~(G - 1);
+  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  uint32_t my_t = NONCONV, my_s = 0;
+  for (uint32_t r = 0; r < G; ++r) {
+    const int owner = (int)(r * R + gidx);
+    const uint32_t om = __shfl(m, owner);
+    const uint32_t ocb = __shfl(cbase, owner);
+    const uint32_t oex = __shfl(exact, owner);
+    const int oisx = __shfl((int)is_exact, owner);
+    const uint32_t olen = __shfl(len, owner);
+    uint64_t o0 = __shfl(sy0, owner), o1 = __shfl(sy1, owner), orr = __shfl(rs, owner);
+    const bool act = om > 0 && om <= G;
+    uint32_t s = tb.q0s;
+    if (act) s = oisx ? oex : ((uint32_t)a.pss_states[ocb + (gi < om ? gi : om - 1)] << SHIFT);
+    uint32_t res_t = NONCONV, res_s = 0;
+    // check after t symbols, then read symbol t; the symbol window shifts down
+    for (uint32_t t = 0; t <= (uint32_t)SPEC_WIN; ++t) {
+      const uint32_t lead = __shfl(s, (int)gl);
+      const unsigned long long ne = __ballot(act && s != lead);
+      const bool gdone = ((ne >> gl) & gmask) == 0;
+      if (act && gdone && res_t == NONCONV && t <= olen) { res_t = t; res_s = s; }
+      const bool pending = act && res_t == NONCONV && t < olen;
+      if (__ballot(pending) == 0) break;
+      const int col = (orr & 1u) ? -1 : (int)(o0 & 3u);
+      s = col < 0 ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (uint32_t)col) & 0xFFFFu);
+      o0 = (o0 >> 2) | (o1 << 62);
+      o1 >>= 2;
+      orr >>= 1;
+    }
+    // hand the result to the chunk's owner lane
+    const int src = (int)(((uint32_t)lane - r * R) * G) & 63;
+    const uint32_t rt = __shfl(res_t, src);
+    const uint32_t rv = __shfl(res_s, src);
+    if ((uint32_t)lane >= r * R && (uint32_t)lane < r * R + R) {
+      my_t = rt;
+      my_s = rv;
+    }
+  }
+
+  // ---- the rest of the chunk from the converging point
+  if (!valid) return;
+  uint32_t out_e = 0, out_cnt = 0;
+  if (my_t != NONCONV) {
+    Sink sink = sink_proto;
+    sink.cnt = 0;
+    out_e = scan_range<ENC, SHIFT, STEP>(a, tb, my_s, lo + my_t, hi, sink);
+    out_cnt = sink.cnt;
+  } else {
+    const uint32_t slot = atomicAdd(a.nc_count, 1u);
+    a.nc_chunk[slot] = (uint32_t)c;
+    a.nc_slot[c] = slot;
+  }
+  a.conv_t[c] = my_t;
+  a.conv_s[c] = my_s;
+  a.end_s[c] = out_e;
+  a.tail_cnt[c] = out_cnt;
+}
+
+// HIST: per-final-state visit histogram in LDS (several patterns); else a
+// total with exact two-symbol counts.
+template <int ENC, int SHIFT, int STEP, bool HIST>
+__global__ __launch_bounds__(kScanBlock) void k_spec_tail(ScanArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  if (STEP == 2) copy_to_lds(lds, a.T2, a.n_states * 64u);
+  copy_to_lds(lds + a.lds_t1_off, a.T1, a.n_states * 16u);
+  uint32_t* wl = reinterpret_cast<uint32_t*>(lds + a.lds_w_off);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + a.lds_hist_off);
+  for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x) {
+    wl[i] = a.wtab[i];
+    if (HIST) hist[i] = 0;
+  }
+  __syncthreads();
+  Tab tb{lds, lds + a.lds_t1_off, a.q0s};
+  const uint64_t wpb = blockDim.x >> 6;
+  const uint64_t wave = threadIdx.x >> 6;
+  if constexpr (HIST) {
+    SinkHist proto{wl, hist};
+    for (uint64_t t = blockIdx.x * wpb + wave; t < a.n_tiles; t += gridDim.x * wpb) tile<ENC, SHIFT, STEP>(a, tb, t, proto);
+  } else {
+    SinkTotal proto{wl};
+    for (uint64_t t = blockIdx.x * wpb + wave; t < a.n_tiles; t += gridDim.x * wpb) tile<ENC, SHIFT, STEP>(a, tb, t, proto);
+  }
+  if constexpr (HIST) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x)
+      if (hist[i]) atomicAdd(a.visits + i, (unsigned long long)hist[i]);
+  }
+}
+
+// Non-converged chunks: one wave per chunk, one lane per candidate, each run
+// to the chunk end (tables in global memory; this is the rare path).
+template <int ENC, int SHIFT, int STEP>
+__global__ __launch_bounds__(256) void k_nonconv(ScanArgs a) {
+  const Tab tb{reinterpret_cast<const char*>(a.T2), reinterpret_cast<const char*>(a.T1), a.q0s};
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  const uint32_t n_nc = *a.nc_count;
+  for (uint32_t slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); slot < n_nc; slot += waves) {
+    const uint64_t c = a.nc_chunk[slot];
+    const uint64_t lo = c * a.chunk;
+    const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+    uint32_t m, cbase, exact;
+    bool is_exact;
+    chunk_header<ENC, SHIFT>(a, tb, lo, m, cbase, exact, is_exact);
+    if (lane == 0) a.nc_m[slot] = m;
+    for (uint32_t b = 0; b < m; b += 64) {
+      const uint32_t i = b + lane;
+      const bool live = i < m;
+      uint32_t s = is_exact ? exact : ((uint32_t)a.pss_states[cbase + (live ? i : 0)] << SHIFT);
+      const uint32_t s0 = s;
+      SinkGlobal none{a.wtab, nullptr};
+      s = scan_range<ENC, SHIFT, STEP>(a, tb, s, lo, hi, none);
+      if (live) {
+        a.nc_cand[(uint64_t)slot * a.max_cand + i] = s0;
+        a.nc_end[(uint64_t)slot * a.max_cand + i] = s;
+      }
+    }
+  }
+}
+
+// The join: each chunk's first state is its predecessor's last state.  A
+// converged chunk is a constant map; runs of non-converged chunks are walked
+// in order from the nearest converged predecessor.
+__global__ void k_compose(ScanArgs a) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > a.n_chunks) return;
+  if (c > 0 && a.conv_t[c - 1] == NONCONV) return;
+  uint32_t s = c == 0 ? a.q0s : a.end_s[c - 1];
+  a.true_start[c] = s;
+  for (uint64_t cc = c; cc < a.n_chunks && a.conv_t[cc] == NONCONV; ++cc) {
+    const uint32_t slot = a.nc_slot[cc];
+    const uint32_t m = a.nc_m[slot];
+    const uint32_t* cand = a.nc_cand + (uint64_t)slot * a.max_cand;
+    uint32_t i = 0;
+    while (i < m && cand[i] != s) ++i;
+    if (i == m) {
+      atomicOr(a.err, 1u);
+      s = a.q0s;
+    } else {
+      s = a.nc_end[(uint64_t)slot * a.max_cand + i];
+    }
+    a.true_start[cc + 1] = s;
+  }
+}
+
+// Count fix-up: recount the chunk prefix before the converging point from the
+// true first state (whole chunk if it did not converge); check the run lands
+// on the converged state; per-chunk totals and the global total.
+template <int ENC, int SHIFT, int STEP>
+__global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t mine = 0;
+  if (c < a.n_chunks) {
+    const Tab tb{reinterpret_cast<const char*>(a.T2), reinterpret_cast<const char*>(a.T1), a.q0s};
+    const uint64_t lo = c * a.chunk;
+    const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+    SinkGlobal sink{a.wtab, per_state ? a.visits : nullptr};
+    const uint32_t s0 = a.true_start[c];
+    if (a.conv_t[c] == NONCONV) {
+      const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
+      if (e != a.true_start[c + 1]) atomicOr(a.err, 2u);
+      mine = sink.cnt;
+    } else {
+      const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, lo + a.conv_t[c], sink);
+      if (e != a.conv_s[c]) atomicOr(a.err, 4u);
+      mine = (uint64_t)sink.cnt + a.tail_cnt[c];
+    }
+    if (a.chunk_cnt) a.chunk_cnt[c] = mine;
+  }
+  // wave sum, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(a.total, (unsigned long long)mine);
+}
+
+// Per-pattern counts: totals for a one-pattern automaton, else visits of each
+// final state spread over the patterns it ends.
+__global__ void k_finalize(ScanArgs a, uint64_t* counts, int per_state) {
+  if (!per_state) {
+    if (threadIdx.x == 0 && a.n_patterns > 0) counts[0] = *a.total;
+    return;
+  }
+  for (uint32_t p = threadIdx.x; p < a.n_patterns; p += blockDim.x) counts[p] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x) {
+    const unsigned long long v = a.visits[i];
+    if (!v) continue;
+    for (uint32_t j = a.acc_out_off[i]; j < a.acc_out_off[i + 1]; ++j)
+      atomicAdd(reinterpret_cast<unsigned long long*>(counts + a.acc_out_ids[j]), v);
+  }
+}
+
+// Exclusive prefix of per-chunk counts (one block; each thread a contiguous
+// run of chunks).  Writes the total to *a.total.
+__global__ void k_scan_counts(ScanArgs a, uint64_t* off) {
+  __shared__ uint64_t part[1024];
+  const uint64_t n = a.n_chunks;
+  const uint64_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint64_t b = threadIdx.x * per;
+  const uint64_t e = b + per < n ? b + per : n;
+  uint64_t s = 0;
+  for (uint64_t i = b; i < e; ++i) s += a.chunk_cnt[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t run = 0;
+    for (uint32_t i = 0; i < blockDim.x; ++i) {
+      const uint64_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    *a.total = run;
+  }
+  __syncthreads();
+  uint64_t run = part[threadIdx.x];
+  for (uint64_t i = b; i < e; ++i) {
+    off[i] = run;
+    run += a.chunk_cnt[i];
+  }
+}
+
+// Second pass of "find": every chunk from its true first state, writing end
+// positions at its offset (ordered within and across chunks).  MODE 1 writes
+// per-chunk records instead.
+template <int ENC, int SHIFT, int STEP, int MODE>
+__global__ __launch_bounds__(kScanBlock) void k_emit(ScanArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  if (STEP == 2) copy_to_lds(lds, a.T2, a.n_states * 64u);
+  copy_to_lds(lds + a.lds_t1_off, a.T1, a.n_states * 16u);
+  __syncthreads();
+  const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_chunks) return;
+  const uint64_t lo = c * a.chunk;
+  const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  const uint32_t s0 = a.true_start[c];
+  if (MODE == 0) {
+    SinkPositions sink{a.acc_out_off, a.acc_out_ids, a.pos_out, a.pat_out, a.chunk_off[c], a.pos_cap};
+    scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
+    if (sink.cnt != a.chunk_cnt[c]) atomicOr(a.err, 8u);
+  } else {
+    uint64_t* row = a.rec_counts + c * a.n_patterns;
+    for (uint32_t p = 0; p < a.n_patterns; ++p) row[p] = 0;
+    SinkRecord sink{a.acc_out_off, a.acc_out_ids, row};
+    const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
+    a.rec_init[c] = s0 >> a.shift;
+    a.rec_last[c] = e >> a.shift;
+    if (e != a.true_start[c + 1]) atomicOr(a.err, 16u);
+  }
+}
+
+// ====================================================================== host runtime
+struct DeviceCopy {
+  int device = -1;
+  char* buf = nullptr;
+  size_t bytes = 0;
+  uint32_t shift = 6;
+  bool t2_exact = true;
+  // per encoding [0] = byte, [1] = 2-bit
+  const uint32_t* T2[2] = {nullptr, nullptr};
+  const uint32_t* T1[2] = {nullptr, nullptr};
+  const uint32_t* wtab = nullptr;
+  const uint32_t* acc_out_off = nullptr;
+  const uint32_t* acc_out_ids = nullptr;
+  const uint32_t* pss_off[kMaxLookback + 1] = {};
+  const uint16_t* pss_states[kMaxLookback + 1] = {};
+  ~DeviceCopy() {
+    if (buf) {
+      int cur = -1;
+      if (hipGetDevice(&cur) == hipSuccess && cur != device) (void)hipSetDevice(device);
+      (void)hipFree(buf);
+      if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+    }
+  }
+};
+
+Dfa::~Dfa() {
+  for (DeviceCopy* d : dev) delete d;
+}
+
+namespace {
+
+std::mutex g_mu;
+
+struct Workspace {
+  char* buf = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+};
+std::map<std::pair<int, void*>, Workspace> g_ws;  // (device, stream) -> workspace
+
+int dev_props(int dev, int& n_cu) {
+  static std::map<int, int> cache;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) { n_cu = it->second; return COEX_OK; }
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return COEX_EDEVICE;
+  cache[dev] = p.multiProcessorCount;
+  n_cu = p.multiProcessorCount;
+  return COEX_OK;
+}
+
+// Column order of the device tables: column j holds the successor on code ord[j].
+const int kOrd2bit[4] = {0, 1, 2, 3};  // A C G T
+const int kOrdByte[4] = {0, 1, 3, 2};  // A C T G ((byte >> 1) & 3)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int upload(Dfa& d, int dev, DeviceCopy*& out) {
+  std::lock_guard<std::mutex> lk(d.mu);
+  if ((int)d.dev.size() > dev && d.dev[dev]) { out = d.dev[dev]; return COEX_OK; }
+  const uint32_t n = d.n_states;
+  auto dc = std::make_unique<DeviceCopy>();
+  dc->device = dev;
+  dc->shift = n <= kMaxStatesStep2 ? 6 : 4;
+  dc->t2_exact = d.max_out <= 15;
+  const uint32_t S = dc->shift;
+  std::vector<uint32_t> w(d.n_accepting);
+  for (uint32_t i = 0; i < d.n_accepting; ++i) {
+    uint32_t s = d.acc_state[i];
+    w[i] = d.out_off[s + 1] - d.out_off[s];
+  }
+  auto weight = [&](uint32_t s) -> uint32_t { return d.out_off[s + 1] - d.out_off[s]; };
+  // host images
+  std::vector<uint32_t> T1[2], T2[2];
+  for (int e = 0; e < 2; ++e) {
+    const int* ord = e == 1 ? kOrd2bit : kOrdByte;
+    T1[e].resize((size_t)n * 4);
+    for (uint32_t s = 0; s < n; ++s)
+      for (int j = 0; j < 4; ++j) {
+        uint32_t t = d.delta[s * 4 + ord[j]];
+        T1[e][s * 4 + j] = (t << S) | ((uint32_t)(d.acc_index[t] + 1) << 16);
+      }
+    if (S == 6) {
+      T2[e].resize((size_t)n * 16);
+      for (uint32_t s = 0; s < n; ++s)
+        for (int g = 0; g < 16; ++g) {
+          uint32_t s1 = d.delta[s * 4 + ord[g & 3]];
+          uint32_t s2 = d.delta[s1 * 4 + ord[g >> 2]];
+          uint32_t cnt = weight(s1) + weight(s2);
+          if (!dc->t2_exact) cnt = cnt ? 1u : 0u;
+          T2[e][s * 16 + g] = (s2 << 6) | (cnt << 24);
+        }
+    }
+  }
+  std::vector<uint32_t> aoff(d.n_accepting + 1, 0), aids;
+  for (uint32_t i = 0; i < d.n_accepting; ++i) {
+    uint32_t s = d.acc_state[i];
+    aids.insert(aids.end(), d.out_ids.begin() + d.out_off[s], d.out_ids.begin() + d.out_off[s + 1]);
+    aoff[i + 1] = (uint32_t)aids.size();
+  }
+  // layout
+  struct Part { const void* src; size_t bytes; size_t off; };
+  std::vector<Part> parts;
+  size_t off = 0;
+  auto add = [&](const void* src, size_t bytes) {
+    parts.push_back({src, bytes, off});
+    off = align_up(off + std::max<size_t>(bytes, 16), 256);
+    return parts.size() - 1;
+  };
+  size_t iT2[2] = {0, 0}, iT1[2];
+  for (int e = 0; e < 2; ++e) {
+    if (S == 6) iT2[e] = add(T2[e].data(), T2[e].size() * 4);
+    iT1[e] = add(T1[e].data(), T1[e].size() * 4);
+  }
+  size_t iw = add(w.data(), w.size() * 4);
+  size_t iao = add(aoff.data(), aoff.size() * 4);
+  size_t iai = add(aids.data(), aids.size() * 4);
+  size_t ipo[kMaxLookback + 1], ips[kMaxLookback + 1];
+  for (uint32_t k = 1; k <= kMaxLookback; ++k) {
+    ipo[k] = add(d.pss[k].off.data(), d.pss[k].off.size() * 4);
+    ips[k] = add(d.pss[k].states.data(), d.pss[k].states.size() * 2);
+  }
+  dc->bytes = off;
+  if (hipMalloc(&dc->buf, off) != hipSuccess) { dc->buf = nullptr; return COEX_ENOMEM; }
+  std::vector<char> img(off, 0);
+  for (auto& p : parts)
+    if (p.bytes) std::memcpy(img.data() + p.off, p.src, p.bytes);
+  if (hipMemcpy(dc->buf, img.data(), off, hipMemcpyHostToDevice) != hipSuccess) return COEX_EDEVICE;
+  auto at = [&](size_t i) { return dc->buf + parts[i].off; };
+  for (int e = 0; e < 2; ++e) {
+    dc->T2[e] = S == 6 ? reinterpret_cast<const uint32_t*>(at(iT2[e])) : nullptr;
+    dc->T1[e] = reinterpret_cast<const uint32_t*>(at(iT1[e]));
+  }
+  dc->wtab = reinterpret_cast<const uint32_t*>(at(iw));
+  dc->acc_out_off = reinterpret_cast<const uint32_t*>(at(iao));
+  dc->acc_out_ids = reinterpret_cast<const uint32_t*>(at(iai));
+  for (uint32_t k = 1; k <= kMaxLookback; ++k) {
+    dc->pss_off[k] = reinterpret_cast<const uint32_t*>(at(ipo[k]));
+    dc->pss_states[k] = reinterpret_cast<const uint16_t*>(at(ips[k]));
+  }
+  if ((int)d.dev.size() <= dev) d.dev.resize(dev + 1, nullptr);
+  d.dev[dev] = dc.release();
+  out = d.dev[dev];
+  return COEX_OK;
+}
+
+// Grow-only scratch per (device, stream).
+int workspace(int dev, void* stream, size_t bytes, char*& out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace& w = g_ws[{dev, stream}];
+  if (w.bytes < bytes) {
+    if (w.buf) {
+      if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return COEX_EDEVICE;
+      (void)hipFree(w.buf);
+      w.buf = nullptr;
+      w.bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    if (hipMalloc(&w.buf, want) != hipSuccess) { w.buf = nullptr; return COEX_ENOMEM; }
+    w.bytes = want;
+    w.device = dev;
+  }
+  out = w.buf;
+  return COEX_OK;
+}
+
+struct Plan {
+  uint32_t shift, step, k, group, max_cand, blocks, lds_bytes;
+  uint64_t chunk, n_chunks, n_tiles;
+  bool hist;
+  int enc;
+};
+
+int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex_opts* o, int n_cu, Plan& P,
+              bool force_hist) {
+  P.enc = sq.encoding == COEX_ENC_2BIT ? 1 : 0;
+  P.shift = dc.shift;
+  if (o && o->step > 2) return COEX_EINVAL;
+  P.step = (o && o->step) ? o->step : (dc.shift == 6 ? 2u : 1u);
+  if (P.step == 2 && dc.shift != 6) return COEX_EUNSUPPORTED;
+  // lookback
+  if (o && o->lookback) {
+    if (o->lookback > kMaxLookback) return COEX_EINVAL;
+    P.k = o->lookback;
+  } else {
+    P.k = kMaxLookback;
+    for (uint32_t k = 1; k <= kMaxLookback; ++k)
+      if (d.pss[k].max_size <= 8) { P.k = k; break; }
+    if (d.pss[P.k].max_size > 8)
+      for (uint32_t k = 1; k <= kMaxLookback; ++k)
+        if (d.pss[k].max_size <= 64) { P.k = k; break; }
+  }
+  const uint32_t mx = std::max<uint32_t>(1, d.pss[P.k].max_size);
+  P.max_cand = mx;
+  if (o && o->width) {
+    if (o->width > 64 || (o->width & (o->width - 1))) return COEX_EINVAL;
+    P.group = o->width;
+  } else {
+    uint32_t g = 1;
+    while (g < mx && g < 64) g <<= 1;
+    P.group = g;
+  }
+  const uint64_t n = sq.n_bases;
+  if (o && o->chunk) {
+    P.chunk = o->chunk;
+  } else {
+    const uint64_t lanes = (uint64_t)n_cu * 2048;
+    uint64_t c = (n + lanes - 1) / lanes;
+    c = std::max<uint64_t>(512, align_up(c, 512));
+    // bound the non-converged scratch (chunks * candidates * 8 bytes) to 512 MiB
+    while ((n / c + 1) * (uint64_t)mx * 8 > (512ull << 20)) c *= 2;
+    P.chunk = c;
+  }
+  P.n_chunks = n == 0 ? 0 : (n + P.chunk - 1) / P.chunk;
+  P.n_tiles = (P.n_chunks + TILE - 1) / TILE;
+  P.hist = force_hist || d.n_patterns > 1 || (P.step == 2 && !dc.t2_exact);
+  return COEX_OK;
+}
+
+template <int ENC, int SHIFT, int STEP, bool HIST>
+void launch_spec(const Plan& P, const ScanArgs& a, int n_cu, hipStream_t st) {
+  auto kern = k_spec_tail<ENC, SHIFT, STEP, HIST>;
+  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+  const uint64_t want = (P.n_tiles + (kScanBlock / 64) - 1) / (kScanBlock / 64);
+  const uint32_t per_cu = P.lds_bytes <= 80 * 1024 ? 2 : 1;
+  const uint64_t cap = (uint64_t)n_cu * per_cu;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kScanBlock), P.lds_bytes, st, a);
+}
+
+template <int ENC, int SHIFT, int STEP>
+void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint64_t* counts, bool emit_counts) {
+  hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, a, counts, emit_counts ? a.n_patterns : 0u);
+  if (P.n_chunks == 0) {
+    if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
+    return;
+  }
+  if (P.hist) launch_spec<ENC, SHIFT, STEP, true>(P, a, n_cu, st);
+  else launch_spec<ENC, SHIFT, STEP, false>(P, a, n_cu, st);
+  constexpr int DSTEP = SHIFT == 6 ? 2 : 1;  // global-table kernels always use the widest step
+  hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), 0, st, a);
+  const uint32_t cb = (uint32_t)((P.n_chunks + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_compose, dim3(cb), dim3(256), 0, st, a);
+  const uint32_t fb = (uint32_t)((P.n_chunks + 255) / 256);
+  hipLaunchKernelGGL((k_fixup<ENC, SHIFT, DSTEP>), dim3(fb), dim3(256), 0, st, a, (int)P.hist);
+  if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
+}
+
+// Everything a scan call shares: validation, upload, plan, workspace, args.
+struct Call {
+  int dev = 0, n_cu = 0;
+  DeviceCopy* dc = nullptr;
+  Plan P{};
+  ScanArgs a{};
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  uint64_t* chunk_off = nullptr;
+};
+
+int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* stream, bool force_hist,
+            bool need_chunk_cnt, Call& C) {
+  if (!h || !seq) return COEX_EINVAL;
+  Dfa& d = *const_cast<Dfa*>(reinterpret_cast<const Dfa*>(h));
+  if (seq->encoding != COEX_ENC_BYTE && seq->encoding != COEX_ENC_2BIT) return COEX_EINVAL;
+  if (seq->n_bases > 0 && !seq->bases) return COEX_EINVAL;
+  if (((uintptr_t)seq->bases & 15) || ((uintptr_t)seq->n_mask & 15)) return COEX_EINVAL;
+  if (hipGetDevice(&C.dev) != hipSuccess) return COEX_EDEVICE;
+  int rc = dev_props(C.dev, C.n_cu);
+  if (rc) return rc;
+  rc = upload(d, C.dev, C.dc);
+  if (rc) return rc;
+  rc = make_plan(d, *C.dc, *seq, o, C.n_cu, C.P, force_hist);
+  if (rc) return rc;
+  Plan& P = C.P;
+  // chunk counts must fit the 32-bit per-chunk tail counter
+  if (P.chunk > (0xFFFFFFFFull / std::max<uint32_t>(1, 2 * d.max_out + 1))) return COEX_EINVAL;
+  const uint32_t S = P.shift;
+  const uint32_t n = d.n_states;
+  const uint32_t t1_off = P.step == 2 ? n * 64 : 0;
+  const uint32_t w_off = t1_off + n * 16;
+  const uint32_t h_off = w_off + (uint32_t)align_up(d.n_accepting * 4, 16);
+  P.lds_bytes = h_off + (uint32_t)align_up(d.n_accepting * 4, 16) + 16;
+  // workspace layout
+  const uint64_t nc = P.n_chunks;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o2 = off; off = align_up(off + std::max<size_t>(bytes, 8), 256); return o2; };
+  size_t o_ct = take(nc * 4), o_cs = take(nc * 4), o_es = take(nc * 4), o_tc = take(nc * 4);
+  size_t o_ncc = take(4), o_nch = take(nc * 4), o_nsl = take(nc * 4), o_nm = take(nc * 4);
+  size_t o_nca = take(nc * P.max_cand * 4), o_nen = take(nc * P.max_cand * 4);
+  size_t o_ts = take((nc + 1) * 4), o_vis = take((size_t)d.n_accepting * 8), o_tot = take(8), o_err = take(4);
+  size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
+  rc = workspace(C.dev, stream, off, C.ws);
+  if (rc) return rc;
+  C.st = (hipStream_t)stream;
+  ScanArgs& a = C.a;
+  char* w = C.ws;
+  a.bases = reinterpret_cast<const uint8_t*>(seq->bases);
+  a.nmask = seq->encoding == COEX_ENC_2BIT ? seq->n_mask : nullptr;
+  a.n = seq->n_bases;
+  a.chunk = P.chunk;
+  a.n_chunks = P.n_chunks;
+  a.n_tiles = P.n_tiles;
+  const int e = P.enc;
+  a.T2 = C.dc->T2[e];
+  a.T1 = C.dc->T1[e];
+  a.wtab = C.dc->wtab;
+  a.n_states = n;
+  a.n_acc = d.n_accepting;
+  a.q0s = d.q0 << S;
+  a.lds_t1_off = t1_off;
+  a.lds_w_off = w_off;
+  a.lds_hist_off = h_off;
+  a.pss_off = C.dc->pss_off[P.k];
+  a.pss_states = C.dc->pss_states[P.k];
+  a.k = P.k;
+  a.group = P.group;
+  a.max_cand = P.max_cand;
+  a.conv_t = reinterpret_cast<uint32_t*>(w + o_ct);
+  a.conv_s = reinterpret_cast<uint32_t*>(w + o_cs);
+  a.end_s = reinterpret_cast<uint32_t*>(w + o_es);
+  a.tail_cnt = reinterpret_cast<uint32_t*>(w + o_tc);
+  a.nc_count = reinterpret_cast<uint32_t*>(w + o_ncc);
+  a.nc_chunk = reinterpret_cast<uint32_t*>(w + o_nch);
+  a.nc_slot = reinterpret_cast<uint32_t*>(w + o_nsl);
+  a.nc_m = reinterpret_cast<uint32_t*>(w + o_nm);
+  a.nc_cand = reinterpret_cast<uint32_t*>(w + o_nca);
+  a.nc_end = reinterpret_cast<uint32_t*>(w + o_nen);
+  a.true_start = reinterpret_cast<uint32_t*>(w + o_ts);
+  a.visits = reinterpret_cast<unsigned long long*>(w + o_vis);
+  a.total = reinterpret_cast<unsigned long long*>(w + o_tot);
+  a.err = reinterpret_cast<uint32_t*>(w + o_err);
+  a.chunk_cnt = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_cc) : nullptr;
+  C.chunk_off = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_co) : nullptr;
+  a.chunk_off = C.chunk_off;
+  a.acc_out_off = C.dc->acc_out_off;
+  a.acc_out_ids = C.dc->acc_out_ids;
+  a.n_patterns = d.n_patterns;
+  a.shift = S;
+  return COEX_OK;
+}
+
+void run_pipeline(Call& C, uint64_t* counts, bool emit_counts) {
+  const bool b = C.P.enc == 0;
+  const Plan& P = C.P;
+  if (P.shift == 6 && P.step == 2) {
+    if (b) launch_pipeline<ENC_BYTE, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+    else launch_pipeline<ENC_2BIT, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+  } else if (P.shift == 6) {
+    if (b) launch_pipeline<ENC_BYTE, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+    else launch_pipeline<ENC_2BIT, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+  } else {
+    if (b) launch_pipeline<ENC_BYTE, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+    else launch_pipeline<ENC_2BIT, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+  }
+}
+
+template <int MODE>
+void launch_emit(Call& C) {
+  const uint32_t blocks = (uint32_t)((C.P.n_chunks + kScanBlock - 1) / kScanBlock);
+  // emit kernels always stage both tables (two-symbol table when it exists)
+  C.a.lds_t1_off = C.P.shift == 6 ? C.a.n_states * 64u : 0u;
+  const uint32_t lds = C.a.lds_t1_off + C.a.n_states * 16u + 16u;
+  auto go = [&](auto kern) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(std::max(1u, blocks)), dim3(kScanBlock), lds, C.st, C.a);
+  };
+  const bool b = C.P.enc == 0;
+  if (C.P.shift == 6) {
+    if (b) go(k_emit<ENC_BYTE, 6, 2, MODE>); else go(k_emit<ENC_2BIT, 6, 2, MODE>);
+  } else {
+    if (b) go(k_emit<ENC_BYTE, 4, 1, MODE>); else go(k_emit<ENC_2BIT, 4, 1, MODE>);
+  }
+}
+
+int check_err(Call& C) {
+  uint32_t e = 0;
+  if (hipMemcpyAsync(&e, C.a.err, 4, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
+  if (hipStreamSynchronize(C.st) != hipSuccess) return COEX_EDEVICE;
+  return e ? COEX_EINTERNAL : COEX_OK;
+}
+
+}  // namespace
+}  // namespace coex
+
+// ====================================================================== C ABI
+using coex::Dfa;
+
+extern "C" {
+
+int coex_compile_kmers(const char* const* kmers, uint32_t n, coex_dfa** out) {
+  if (!kmers || !out || n == 0) return COEX_EINVAL;
+  try {
+    std::vector<std::string> v;
+    v.reserve(n);
+    for (uint32_t i = 0; i < n; ++i) {
+      if (!kmers[i]) return COEX_EINVAL;
+      v.emplace_back(kmers[i]);
+    }
+    std::unique_ptr<Dfa> d;
+    int rc = coex::compile_kmers(v, d);
+    if (rc) return rc;
+    *out = reinterpret_cast<coex_dfa*>(d.release());
+    return COEX_OK;
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_compile_regex(const char* regex, coex_dfa** out) {
+  if (!regex || !out) return COEX_EINVAL;
+  try {
+    std::unique_ptr<Dfa> d;
+    int rc = coex::compile_regex(regex, d);
+    if (rc) return rc;
+    *out = reinterpret_cast<coex_dfa*>(d.release());
+    return COEX_OK;
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_dfa_from_table(const uint32_t* delta, uint32_t n_states, uint32_t q0, const uint32_t* out_offsets,
+                        const uint32_t* out_ids, uint32_t n_patterns, coex_dfa** out) {
+  if (!out) return COEX_EINVAL;
+  try {
+    std::unique_ptr<Dfa> d;
+    int rc = coex::from_table(delta, n_states, q0, out_offsets, out_ids, n_patterns, d);
+    if (rc) return rc;
+    *out = reinterpret_cast<coex_dfa*>(d.release());
+    return COEX_OK;
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_dfa_info(const coex_dfa* h, coex_dfa_info_t* info) {
+  if (!h || !info) return COEX_EINVAL;
+  const Dfa& d = *reinterpret_cast<const Dfa*>(h);
+  info->n_states = d.n_states;
+  info->n_patterns = d.n_patterns;
+  info->n_accepting = d.n_accepting;
+  info->q0 = d.q0;
+  info->sync_depth = d.sync_depth;
+  info->max_out = d.max_out;
+  info->max_pss[0] = d.n_states;
+  for (uint32_t k = 1; k <= coex::kMaxLookback; ++k) info->max_pss[k] = d.pss[k].max_size;
+  return COEX_OK;
+}
+
+int coex_dfa_export(const coex_dfa* h, uint32_t* delta, uint32_t* out_offsets, uint32_t* out_ids) {
+  if (!h) return COEX_EINVAL;
+  const Dfa& d = *reinterpret_cast<const Dfa*>(h);
+  if (delta) std::memcpy(delta, d.delta.data(), d.delta.size() * 4);
+  if (out_offsets) std::memcpy(out_offsets, d.out_off.data(), d.out_off.size() * 4);
+  if (out_ids && !d.out_ids.empty()) std::memcpy(out_ids, d.out_ids.data(), d.out_ids.size() * 4);
+  return COEX_OK;
+}
+
+void coex_dfa_free(coex_dfa* h) { delete reinterpret_cast<Dfa*>(h); }
+
+int coex_count(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, const coex_opts* opts,
+               void* stream) {
+  if (!counts_dev) return COEX_EINVAL;
+  try {
+    coex::Call C;
+    int rc = coex::prepare(dfa, seq, opts, stream, false, false, C);
+    if (rc) return rc;
+    coex::run_pipeline(C, counts_dev, true);
+    if (hipGetLastError() != hipSuccess) return COEX_EDEVICE;
+    if (opts && (opts->flags & COEX_FLAG_CHECK)) return coex::check_err(C);
+    return COEX_OK;
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
+              uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream) {
+  if (!n_found || (capacity && !pos_dev)) return COEX_EINVAL;
+  try {
+    coex::Call C;
+    int rc = coex::prepare(dfa, seq, opts, stream, false, true, C);
+    if (rc) return rc;
+    coex::run_pipeline(C, nullptr, false);
+    uint64_t total = 0;
+    if (C.P.n_chunks) {
+      hipLaunchKernelGGL(coex::k_scan_counts, dim3(1), dim3(1024), 0, C.st, C.a, C.chunk_off);
+    }
+    if (hipMemcpyAsync(&total, C.a.total, 8, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
+    uint32_t e = 0;
+    if (hipMemcpyAsync(&e, C.a.err, 4, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
+    if (hipStreamSynchronize(C.st) != hipSuccess) return COEX_EDEVICE;
+    if (e) return COEX_EINTERNAL;
+    *n_found = total;
+    if (total > capacity) return COEX_ECAPACITY;
+    if (total == 0) return COEX_OK;
+    C.a.pos_out = pos_dev;
+    C.a.pat_out = pattern_dev;
+    C.a.pos_cap = capacity;
+    coex::launch_emit<0>(C);
+    if (hipGetLastError() != hipSuccess) return COEX_EDEVICE;
+    return coex::check_err(C);
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_count_chunks(const coex_dfa* dfa, const coex_seq* seq, uint32_t chunk, uint32_t* init_dev,
+                      uint32_t* last_dev, uint64_t* counts_dev, void* stream) {
+  if (!init_dev || !last_dev || !counts_dev || chunk == 0) return COEX_EINVAL;
+  try {
+    coex_opts o{};
+    o.chunk = chunk;
+    coex::Call C;
+    int rc = coex::prepare(dfa, seq, &o, stream, false, true, C);
+    if (rc) return rc;
+    coex::run_pipeline(C, nullptr, false);
+    C.a.rec_counts = counts_dev;
+    C.a.rec_init = init_dev;
+    C.a.rec_last = last_dev;
+    if (C.P.n_chunks == 0) {
+      // one empty chunk: (q0, q0, zeros)
+      const Dfa& d = *reinterpret_cast<const Dfa*>(dfa);
+      uint32_t q = d.q0;
+      if (hipMemcpyAsync(init_dev, &q, 4, hipMemcpyHostToDevice, C.st) != hipSuccess ||
+          hipMemcpyAsync(last_dev, &q, 4, hipMemcpyHostToDevice, C.st) != hipSuccess)
+        return COEX_EDEVICE;
+      std::vector<uint64_t> z(std::max<uint32_t>(1, d.n_patterns), 0);
+      if (d.n_patterns &&
+          hipMemcpyAsync(counts_dev, z.data(), 8 * d.n_patterns, hipMemcpyHostToDevice, C.st) != hipSuccess)
+        return COEX_EDEVICE;
+      if (hipStreamSynchronize(C.st) != hipSuccess) return COEX_EDEVICE;
+      return COEX_OK;
+    }
+    coex::launch_emit<1>(C);
+    if (hipGetLastError() != hipSuccess) return COEX_EDEVICE;
+    return coex::check_err(C);
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_seq* seqs, uint32_t n_seq,
+                       uint64_t* counts_dev, const coex_opts* opts, void* stream) {
+  (void)dfas; (void)n_dfa; (void)seqs; (void)n_seq; (void)counts_dev; (void)opts; (void)stream;
+  return COEX_EUNSUPPORTED;
+}
+
+const char* coex_strerror(int s) {
+  switch (s) {
+    case COEX_OK: return "ok";
+    case COEX_EINVAL: return "invalid argument";
+    case COEX_EALPHABET: return "pattern empty or outside A,C,G,T";
+    case COEX_ETOOBIG: return "automaton too large for the device tables";
+    case COEX_ENOMEM: return "out of memory";
+    case COEX_ECAPACITY: return "result buffer too small";
+    case COEX_EDEVICE: return "HIP runtime error";
+    case COEX_EUNSUPPORTED: return "unsupported option combination";
+    case COEX_ESYNTAX: return "regular expression syntax error or empty match";
+    case COEX_EINTERNAL: return "device consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+const char* coex_version(void) { return "coex 0.1 gfx950"; }
+
+}  // extern "C"

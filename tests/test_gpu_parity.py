@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+bit-exact, on seeded inputs spanning several tiles and a ragged tail, the
+edge cases of the method, and every option that must not change results."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def coex():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1509_01506_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev_bytes(coex, arr):
+    return coex.to_device(np.asarray(arr, dtype=np.uint8), encoding=coex.ENC_BYTE)
+
+
+def dev_2bit(coex, seq_bytes):
+    packed, mask = synth.bytes_to_2bit(seq_bytes)
+    return coex.to_device(packed, n=seq_bytes.size, encoding=coex.ENC_2BIT, nmask=mask), packed, mask
+
+
+def gpu_counts(coex, dfa, s, **kw):
+    return coex.count(dfa, s, check=True, **kw).cpu().numpy().view(np.uint64)
+
+
+def test_small_config_count_and_positions(coex):
+    seq, kmers = configs.small()
+    say("small: n", seq.size, "kmer", kmers)
+    d = coex.Dfa.kmers(kmers)
+    s = dev_bytes(coex, seq)
+    c = gpu_counts(coex, d, s, chunk=configs.SMALL_CHUNK)
+    ec, epos, epat = oracle.count_kmers(kmers, oracle.byte_seq(seq), positions=True)
+    assert c.tolist() == ec.tolist()
+    pos, pat = coex.find(d, s, chunk=configs.SMALL_CHUNK)
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+    assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
+
+
+def _kmer_sets():
+    out = []
+    for seed in range(3):
+        st = synth.Stream(seed, 5)
+        pats = [synth.random_kmers(seed * 31 + j, 1, 2 + st.below(9))[0] for j in range(10)]
+        pats += [pats[1], pats[3][-2:]]       # duplicate id, suffix pattern
+        out.append(pats)
+    out.append(["A", "AA", "AAA", "AAAA"])        # output sets of size up to 4
+    return out
+
+
+@pytest.mark.parametrize("enc", ["byte", "2bit"])
+def test_invariance_over_options(coex, enc):
+    n = 40_003
+    seq = synth.markov_bytes(21, n, with_n=True)
+    seq[5000:5003] = ord("N")
+    seq[::977] = ord("n")
+    if enc == "byte":
+        seq[3::1013] = ord("a")
+        s = dev_bytes(coex, seq)
+    else:
+        s, _, _ = dev_2bit(coex, seq)
+    for pats in _kmer_sets():
+        d = coex.Dfa.kmers(pats)
+        expect = oracle.count_kmers(pats, oracle.byte_seq(seq))[0].tolist()
+        for chunk in [1, 7, 16, 63, 64, 100, 512, 1000, 4096, n - 1, n, n + 5, 0]:
+            for (width, lookback, step) in [(0, 0, 0), (1, 1, 1), (2, 1, 2), (8, 2, 0), (64, 1, 0), (4, 8, 2)]:
+                say("invariance", enc, pats[:2], chunk, width, lookback, step)
+                got = gpu_counts(coex, d, s, chunk=chunk, width=width, lookback=lookback, step=step)
+                assert got.tolist() == expect, (pats, chunk, width, lookback, step)
+
+
+def test_positions_multi_pattern(coex):
+    n = 100_000
+    seq = synth.markov_bytes(22, n, with_n=True)
+    pats = ["ACG", "CG", "G", "TTAGG", "AGG", "ACGT", "ACG"]
+    d = coex.Dfa.kmers(pats)
+    _, epos, epat = oracle.count_kmers(pats, oracle.byte_seq(seq), positions=True)
+    for chunk in [0, 1000, 4097]:
+        for enc in ["byte", "2bit"]:
+            s = dev_bytes(coex, seq) if enc == "byte" else dev_2bit(coex, seq)[0]
+            say("positions", enc, chunk)
+            pos, pat = coex.find(d, s, chunk=chunk)
+            assert pos.cpu().numpy().tolist() == epos.tolist()
+            assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
+    # capacity too small reports the required size
+    s = dev_bytes(coex, seq)
+    with pytest.raises(coex.CoexError) as e:
+        coex.find(d, s, capacity=3)
+    assert e.value.name == "ECAPACITY"
+
+
+def test_regex_mid_fraction(coex):
+    n = configs.MID_N // 64
+    seq, rx = configs.mid(n)
+    say("mid/64 regex", rx, n)
+    d = coex.Dfa.regex(rx)
+    s = dev_bytes(coex, seq)
+    m, epos = oracle.Regex(rx).scan(oracle.byte_seq(seq), positions=True)
+    assert gpu_counts(coex, d, s).tolist() == [m]
+    pos, _ = coex.find(d, s)
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+
+
+def test_random_regexes(coex):
+    n = 60_000
+    seq = synth.markov_bytes(23, n, with_n=True)
+    s = dev_bytes(coex, seq)
+    s2 = dev_2bit(coex, seq)[0]
+    for seed in range(12):
+        rx = synth.random_regex(seed)
+        try:
+            d = coex.Dfa.regex(rx)
+        except coex.CoexError:
+            continue
+        m, epos = oracle.Regex(rx).scan(oracle.byte_seq(seq), positions=True)
+        for chunk in [0, 333, 2048]:
+            say("regex", rx, chunk)
+            assert gpu_counts(coex, d, s, chunk=chunk).tolist() == [m]
+            assert gpu_counts(coex, d, s2, chunk=chunk).tolist() == [m]
+        pos, _ = coex.find(d, s, chunk=1000)
+        assert pos.cpu().numpy().tolist() == epos.tolist()
+
+
+def test_genome_fraction(coex):
+    n = configs.GENOME_N // 64
+    packed, mask, kmers = configs.genome(n)
+    say("genome/64", n)
+    d = coex.Dfa.kmers(kmers)
+    s = coex.to_device(packed, n=n, encoding=coex.ENC_2BIT, nmask=mask)
+    expect = oracle.count_kmers(kmers, oracle.twobit_seq(packed, mask, n))[0]
+    assert gpu_counts(coex, d, s).tolist() == expect.tolist()
+    assert gpu_counts(coex, d, s, chunk=1 << 16, lookback=1, width=64).tolist() == expect.tolist()
+
+
+def _parity_table():
+    return np.array([1, 0, 0, 0, 0, 1, 1, 1], np.uint32), 0, np.array([0, 0, 1], np.uint32), np.array([0], np.uint32)
+
+
+def test_tables_and_nonconverging(coex):
+    n = 30_011
+    seq = synth.markov_bytes(24, n, with_n=True)
+    s = dev_bytes(coex, seq)
+    s2 = dev_2bit(coex, seq)[0]
+    tables = [(_parity_table(), 1)]
+    for seed in range(4):
+        dl, q0, off, ids = synth.random_table(seed, 20 + 30 * seed, 5)
+        tables.append(((dl, q0, off, ids), 5))
+    for (dl, q0, off, ids), P in tables:
+        d = coex.Dfa.table(dl, q0, off, ids, P)
+        t = oracle.make_table(dl, q0, off, ids, P)
+        ec, epos, epat, _ = oracle.scan_table(t, oracle.byte_seq(seq), positions=True)
+        for chunk in [0, 50, 999]:
+            say("table", dl.size // 4, chunk)
+            assert gpu_counts(coex, d, s, chunk=chunk).tolist() == ec.tolist()
+            assert gpu_counts(coex, d, s2, chunk=chunk, width=1).tolist() == ec.tolist()
+        pos, pat = coex.find(d, s, chunk=777)
+        assert pos.cpu().numpy().tolist() == epos.tolist()
+        assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
+
+
+def test_count_chunks_records(coex):
+    n = 50_000
+    seq = synth.markov_bytes(25, n, with_n=True)
+    s = dev_bytes(coex, seq)
+    # a table automaton keeps its numbering: records compare state by state
+    dl, q0, off, ids = synth.random_table(7, 40, 3)
+    d = coex.Dfa.table(dl, q0, off, ids, 3)
+    t = oracle.make_table(dl, q0, off, ids, 3)
+    for n_chunks in [1, 10, 50]:
+        chunk = n // n_chunks
+        say("records", n_chunks)
+        init, last, cnt = coex.count_chunks(d, s, chunk)
+        r = oracle.kcoex(t, oracle.byte_seq(seq), n_chunks)
+        # the join's pick per chunk: the record whose init is the true state
+        cur, picks = t.q0, []
+        for c in range(n_chunks):
+            idx = [i for i in range(len(r.cr_init)) if r.cr_chunk[i] == c and r.cr_init[i] == cur][0]
+            picks.append(idx)
+            cur = int(r.cr_last[idx])
+        assert init.cpu().numpy().tolist() == [int(r.cr_init[i]) for i in picks]
+        assert last.cpu().numpy().tolist() == [int(r.cr_last[i]) for i in picks]
+        assert cnt.cpu().numpy().tolist() == [r.cr_counts[i].tolist() for i in picks]
+
+
+def test_edge_cases(coex):
+    k12 = synth.random_kmers(9, 1, 12)[0]
+    d = coex.Dfa.kmers([k12, "ACGT"])
+    cases = {
+        "empty": b"",
+        "one": b"A",
+        "all_N": b"N" * 5000,
+        "short": (k12 + "A").encode(),
+        "spanning": ("TT" + k12 + "GG" + k12).encode(),
+        "n_at_boundaries": ("ACGTN" * 200 + k12 * 3).encode(),
+        "lowercase": (k12.lower() + "acgt" + "xyz" + k12).encode(),
+        "all_bytes": bytes(range(256)) * 20 + k12.encode(),
+    }
+    for name, text in cases.items():
+        arr = np.frombuffer(text, dtype=np.uint8).copy() if text else np.zeros(0, np.uint8)
+        expect = oracle.count_kmers([k12, "ACGT"], oracle.byte_seq(arr))[0].tolist()
+        s = dev_bytes(coex, arr) if arr.size else coex.to_device(np.zeros(16, np.uint8), n=0)
+        for chunk in [0, 4, 5, 16, 64, 1000]:
+            say("edge", name, chunk)
+            assert gpu_counts(coex, d, s, chunk=chunk).tolist() == expect, (name, chunk)
+        if arr.size:
+            s2 = dev_2bit(coex, arr)[0]
+            assert gpu_counts(coex, d, s2, chunk=4).tolist() == expect, name
+    # a 100-mer: chunks shorter than the synchronising depth
+    long = synth.random_kmers(10, 1, 100)[0]
+    d = coex.Dfa.kmers([long, long[:30]])
+    text = synth.markov_bytes(26, 20_000).tobytes().decode()
+    text = text[:5000] + long + text[5000:9000] + long + long + text[9000:]
+    arr = np.frombuffer(text.encode(), dtype=np.uint8).copy()
+    expect = oracle.count_kmers([long, long[:30]], oracle.byte_seq(arr))[0].tolist()
+    s = dev_bytes(coex, arr)
+    for chunk in [16, 64, 99, 512]:
+        say("long pattern", chunk)
+        assert gpu_counts(coex, d, s, chunk=chunk).tolist() == expect
+
+
+def test_full_small_and_mid(coex):
+    # the small and mid workloads at full size, with the bench's launch choices
+    seq, kmers = configs.small()
+    d = coex.Dfa.kmers(kmers)
+    s = dev_bytes(coex, seq)
+    assert gpu_counts(coex, d, s, chunk=configs.SMALL_CHUNK).tolist() == \
+        oracle.count_kmers(kmers, oracle.byte_seq(seq))[0].tolist()
+    seq, rx = configs.mid()
+    say("mid full", rx)
+    d = coex.Dfa.regex(rx)
+    s = dev_bytes(coex, seq)
+    m, epos = oracle.Regex(rx).scan(oracle.byte_seq(seq), positions=True)
+    assert gpu_counts(coex, d, s).tolist() == [m]
+    pos, _ = coex.find(d, s)
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+
+
+def test_full_genome(coex):
+    # the 3.2e9-base workload in the bench's launch configuration; the oracle
+    # computes all 64 counts over the whole sequence
+    import torch
+    packed, mask, kmers = configs.genome()
+    n = configs.GENOME_N
+    say("genome full: generated")
+    d = coex.Dfa.kmers(kmers)
+    s = coex.to_device(packed, n=n, encoding=coex.ENC_2BIT, nmask=mask)
+    got = gpu_counts(coex, d, s)
+    say("genome full: gpu done", int(got.sum()))
+    expect = oracle.count_kmers(kmers, oracle.twobit_seq(packed, mask, n))[0]
+    say("genome full: oracle done", int(expect.sum()))
+    assert got.tolist() == expect.tolist()
+    del s
+    torch.cuda.empty_cache()
