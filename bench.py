@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the chunked speculative DFA scan on one MI355X.
+
+Default workload (the 3.2-Gbase genome-scale configuration): 3.2e9 bases of a
+first-order Markov source (GC 0.41, 1% N in runs), stored 2-bit packed with a
+1-bit N mask, scanned for 64 random 12-mers (Aho-Corasick automaton of 632
+states) with per-pattern counts.  A step is one coex_count over the whole
+sequence: possible starting states, speculation with ballot convergence, the
+scan of every chunk, the join, the fix-up and the per-pattern reduction.  The
+sequence is resident in HBM before timing starts.
+
+Prints one JSON line:  metric/value (Gbases/s), ms_per_step, a roofline entry
+for the dominant kernel (the speculation + chunk scan kernel, timed with HIP
+events on its stream inside the timed region), and a CPU baseline (the oracle,
+single thread, over the same sequence, which doubles as the exactness check).
+
+  python bench.py [--steps K] [--warmup W] [--workload genome|mid|small]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1509_01506_amd", "csrc", f) for f in ("coex.hip", "kernels.hpp")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the scan kernel from the stored rocprofv3 PMC
+    runs, if they were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        e = t.get(workload)
+        if not e or e.get("source_sha") != kernel_source_sha():
+            return None
+        return e["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def build_workload(name: str):
+    import numpy as np
+    import paper_1509_01506_amd as coex
+    from synth import configs
+    if name == "genome":
+        packed, mask, kmers = configs.genome()
+        n = configs.GENOME_N
+        return dict(
+            n=n, enc=coex.ENC_2BIT, host=(packed, mask), dfa=coex.Dfa.kmers(kmers), patterns=kmers, chunk=0,
+            bytes_per_base=0.375, find=False,
+            desc="genome: 3.2e9 Markov bases (GC 0.41, 1% N runs), 2-bit packed + 1-bit N mask; "
+                 "64 random 12-mers as one Aho-Corasick automaton; per-pattern counts")
+    if name == "mid":
+        seq, rx = configs.mid()
+        return dict(n=seq.size, enc=coex.ENC_BYTE, host=(seq, None), dfa=coex.Dfa.regex(rx), patterns=rx, chunk=0,
+                    bytes_per_base=1.0, find=True,
+                    desc="mid: 256 MiB Markov bytes with 1%% N runs; regex %s (60-state search automaton); "
+                         "count and end positions" % rx)
+    if name == "small":
+        seq, kmers = configs.small()
+        return dict(n=seq.size, enc=coex.ENC_BYTE, host=(seq, None), dfa=coex.Dfa.kmers(kmers), patterns=kmers,
+                    chunk=configs.SMALL_CHUNK, bytes_per_base=1.0, find=True,
+                    desc="small: 1 MiB iid bytes; one random 8-mer (9-state automaton); chunk 64 KiB; "
+                         "count and end positions")
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(name: str, w, gpu_counts):
+    """The oracle (single thread) over the same input: rate and exactness."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    if name == "genome":
+        packed, mask = w["host"]
+        seq = oracle.twobit_seq(packed, mask, w["n"])
+        counts = oracle.count_kmers(w["patterns"], seq)[0]
+    elif name == "mid":
+        counts = np.array([oracle.Regex(w["patterns"]).scan(oracle.byte_seq(w["host"][0]))[0]], dtype=np.uint64)
+    else:
+        counts = oracle.count_kmers(w["patterns"], oracle.byte_seq(w["host"][0]))[0]
+    dt = time.perf_counter() - t0
+    exact = [int(x) for x in counts] == [int(x) for x in gpu_counts]
+    return {"value": round(w["n"] / dt / 1e9, 4), "unit": "Gbases/s", "cores": 1, "kind": "oracle",
+            "sample": "the whole workload (%d bases), one thread, %.1f s" % (w["n"], dt)}, exact
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build scans one GPU's share; the multi-GPU sharding "
+              "(one boundary-state exchange and one count reduction) is described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1509_01506_amd as coex
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    w = build_workload(args.workload)
+    log("workload generated in %.1f s" % (time.perf_counter() - t0))
+    data, mask = w["host"]
+    seq = coex.to_device(data, n=w["n"], encoding=w["enc"], nmask=mask)
+    dfa = w["dfa"]
+    info = dfa.info()
+    torch.cuda.synchronize()
+    log("resident in HBM; automaton %d states" % info.n_states)
+
+    out = torch.empty(max(1, info.n_patterns), dtype=torch.int64, device="cuda")
+
+    def step(timed: bool):
+        coex.count(dfa, seq, out=out, chunk=w["chunk"], timed=timed)
+        if w["find"]:
+            coex.find(dfa, seq, chunk=w["chunk"])
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    coex.profile(reset=True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step(True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    k_ms, k_n = coex.profile(reset=True)
+    k_avg_ms = k_ms / max(1, k_n)
+    gpu_counts = out[: info.n_patterns].cpu().numpy().view(np.uint64)
+    value = w["n"] / (ms_step * 1e-3) / 1e9
+    log("wall %.3f s for %d steps; events %.3f ms/step; scan kernel %.3f ms avg over %d launches"
+        % (wall, args.steps, ms_step, k_avg_ms, k_n))
+
+    algo_bytes = w["n"] * w["bytes_per_base"]
+    achieved = algo_bytes / (k_avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
+    res = {
+        "metric": "Gbases/s scanned (exact counts)",
+        "value": round(value, 2),
+        "unit": "Gbases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "bases": w["n"], "automaton_states": info.n_states,
+                   "patterns": info.n_patterns, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_spec_tail", "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "kernel_ms": round(k_avg_ms, 4),
+                     "algorithmic_bytes_per_launch": int(algo_bytes)},
+    }
+    if not args.no_cpu_baseline:
+        cb, exact = cpu_baseline(args.workload, w, gpu_counts)
+        res["cpu_baseline"] = cb
+        res["exact"] = exact
+        log("oracle: %s; exact=%s" % (cb["sample"], exact))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,7 +85,8 @@ typedef struct {
    step:     symbols per table lookup in the main loop (1 or 2; 2 needs at
              most 1024 states)
    flags:    COEX_FLAG_CHECK: synchronise the stream at the end of the call and
-             return COEX_EINTERNAL if a device-side consistency check failed */
+             return COEX_EINTERNAL if a device-side consistency check failed;
+             COEX_FLAG_TIME: time the scan kernel (coex_profile) */
 typedef struct {
   uint32_t chunk;
   uint32_t width;
@@ -95,6 +96,7 @@ typedef struct {
 } coex_opts;
 
 #define COEX_FLAG_CHECK 1u
+#define COEX_FLAG_TIME 2u  /* record HIP events around the scan kernel (see coex_profile) */
 
 /* Facts about a compiled automaton. */
 typedef struct {
@@ -178,6 +180,14 @@ int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_s
                        uint64_t* counts_dev, const coex_opts* opts, void* stream);
 
 const char* coex_strerror(int status);
+
+/* Instrumentation, not part of the method: total device time (ms) of the
+   scan kernel over the calls made on `stream` with COEX_FLAG_TIME since the
+   last reset, measured with HIP events recorded on that stream around the
+   kernel launch, and the number of such launches.  Waits for those events.
+   reset != 0 starts a new measurement window (at most 4096 launches are
+   recorded per window). */
+int coex_profile(void* stream, double* total_ms, uint64_t* launches, int reset);
 
 /* Version string of the library build. */
 const char* coex_version(void);

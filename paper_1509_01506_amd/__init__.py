@@ -15,18 +15,19 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcoex.so")
+LIB_PATH = os.environ.get("COEX_LIBRARY") or os.path.join(_HERE, "libcoex.so")
 
 ENC_BYTE = 0
 ENC_2BIT = 1
 FLAG_CHECK = 1
+FLAG_TIME = 2
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -5: "ECAPACITY",
           -6: "EDEVICE", -7: "EUNSUPPORTED", -8: "ESYNTAX", -9: "EINTERNAL"}
 
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_find", "coex_count_chunks",
-            "coex_count_batched", "coex_strerror", "coex_version"]
+            "coex_count_batched", "coex_profile", "coex_strerror", "coex_version"]
 
 
 class CoexError(RuntimeError):
@@ -75,6 +76,7 @@ def _lib():
         L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
         L.coex_count_chunks.argtypes = [p, p, u32, p, p, p, p]
         L.coex_count_batched.argtypes = [p, u32, p, u32, p, p, p]
+        L.coex_profile.argtypes = [p, p, p, ci]
         L.coex_strerror.argtypes = [ci]
         L.coex_strerror.restype = ctypes.c_char_p
         L.coex_version.restype = ctypes.c_char_p
@@ -205,8 +207,8 @@ def to_device(data: np.ndarray, n: Optional[int] = None, encoding: int = ENC_BYT
     return DeviceSeq(b, int(n), encoding, m)
 
 
-def _opts(chunk=0, width=0, lookback=0, step=0, check=False) -> _Opts:
-    return _Opts(chunk, width, lookback, step, FLAG_CHECK if check else 0)
+def _opts(chunk=0, width=0, lookback=0, step=0, check=False, timed=False) -> _Opts:
+    return _Opts(chunk, width, lookback, step, (FLAG_CHECK if check else 0) | (FLAG_TIME if timed else 0))
 
 
 def _stream(stream):
@@ -218,14 +220,14 @@ def _stream(stream):
 
 # ------------------------------------------------------------------ scans
 def count(dfa: Dfa, seq: DeviceSeq, out=None, chunk: int = 0, width: int = 0, lookback: int = 0, step: int = 0,
-          check: bool = False, stream=None):
+          check: bool = False, timed: bool = False, stream=None):
     """Per-pattern match counts as an int64 CUDA tensor (the device buffer holds uint64)."""
     import torch
     P = dfa.info().n_patterns
     if out is None:
         out = torch.empty(max(1, P), dtype=torch.int64, device=seq.bases.device)
     s = seq._c()
-    o = _opts(chunk, width, lookback, step, check)
+    o = _opts(chunk, width, lookback, step, check, timed)
     _check(_lib().coex_count(dfa.handle, ctypes.byref(s), out.data_ptr(), ctypes.byref(o), _stream(stream)),
            "count")
     return out[:P]
@@ -284,6 +286,14 @@ def count_batched(dfas: Sequence[Dfa], seqs: Sequence[DeviceSeq], out=None, chun
                                      len(seqs), out.data_ptr(), ctypes.byref(o), _stream(stream)),
            "count_batched")
     return out
+
+
+def profile(stream=None, reset: bool = True):
+    """(total ms, launches) of the scan kernel over timed calls on `stream`."""
+    ms = ctypes.c_double(0.0)
+    k = ctypes.c_uint64(0)
+    _check(_lib().coex_profile(_stream(stream), ctypes.byref(ms), ctypes.byref(k), int(reset)), "profile")
+    return ms.value, int(k.value)
 
 
 def version() -> str:

@@ -37,28 +37,29 @@ def _run(cmd, verbose):
         print(err, file=sys.stderr)
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     """Always recompiles (the driver's build check calls this): the host-only
     compiler with g++, the kernels and runtime with hipcc for gfx950."""
     inc = ["-I", os.path.join(ROOT, "include")]
-    tag = ".tmp%d" % os.getpid()
+    tag = ".tmp%d_%d" % (os.getpid(), abs(hash((out, tuple(defines)))) % 100000)
     sfx = tag.replace(".", "_")
     obj_host = os.path.join(CSRC, "compile%s.o" % sfx)
     obj_dev = os.path.join(CSRC, "coex%s.o" % sfx)
-    tmp = LIB + tag
+    tmp = out + tag
     try:
         _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", "-o", obj_host] + inc +
              [os.path.join(CSRC, "compile.cpp")], verbose)
-        _run([hipcc()] + FLAGS + inc + ["-c", "-o", obj_dev, os.path.join(CSRC, "coex.hip")], verbose)
+        _run([hipcc()] + FLAGS + ["-D" + d for d in defines] + inc +
+             ["-c", "-o", obj_dev, os.path.join(CSRC, "coex.hip")], verbose)
         rocm_lib = "/opt/rocm/lib"
         _run(["g++", "-shared", "-o", tmp, obj_dev, obj_host, "-L" + rocm_lib, "-lamdhip64",
               "-Wl,-rpath," + rocm_lib], verbose)
-        os.replace(tmp, LIB)
+        os.replace(tmp, out)
     finally:
         for f in (obj_host, obj_dev, tmp):
             if os.path.exists(f):
                 os.remove(f)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

@@ -2,10 +2,12 @@
 //
 // Pipeline of one scan (Section III of the paper, re-laid out for one MI355X):
 //   k_init       clears the small device counters;
-//   k_spec_tail  per tile of 64 chunks: possible starting states from the
-//                lookback table, lockstep speculative runs with ballot
-//                convergence (Algorithm 1's converging point), then one scan of
-//                the rest of each chunk from the converged state;
+//   k_spec       per tile of 64 chunks (one wave): possible starting states
+//                from the lookback table, lockstep speculative runs with
+//                ballot convergence (Algorithm 1's converging point);
+//   k_tail       one lane per chunk: one scan of the rest of the chunk from
+//                the converged state, then the join with the predecessor lane
+//                and the prefix recount inside the wave;
 //   k_nonconv    chunks that did not converge inside the window: every
 //                candidate runs to the chunk end (the paper's non-converged
 //                runs), giving the chunk's state map on its candidates;
@@ -20,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -36,7 +39,7 @@
 namespace coex {
 
 // ====================================================================== kernels
-constexpr int kScanBlock = 1024;
+constexpr int kScanBlock = COEX_SCAN_BLOCK;
 
 __device__ __forceinline__ void copy_to_lds(char* dst, const void* src, uint32_t bytes) {
   const uint4* s = reinterpret_cast<const uint4*>(src);
@@ -48,6 +51,7 @@ __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     *a.nc_count = 0;
+    *a.fix_count = 0;
     *a.err = 0;
     *a.total = 0;
   }
@@ -56,87 +60,173 @@ __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
     for (uint32_t i = t; i < n_counts; i += gridDim.x * blockDim.x) counts[i] = 0;
 }
 
-// Candidate list of chunk c: either one exact state (chunk 0, a reset inside
-// the lookback window, or a window that reaches the sequence start) or the
-// PSS table entry of the k-gram before the chunk.
+// The 8 bases before `lo` (lo >= 8): table columns two bits per base (oldest
+// first), A,C,G,T codes the same way, and a reset bit per base.
+template <int ENC>
+__device__ __forceinline__ void lookback8(const ScanArgs& a, uint64_t lo, uint32_t& cols, uint32_t& codes,
+                                          uint32_t& rst) {
+  if constexpr (ENC == ENC_2BIT) {
+    if ((lo & 7) == 0) {
+      cols = *reinterpret_cast<const uint16_t*>(a.bases + ((lo - 8) >> 2));
+      rst = a.nmask ? a.nmask[(lo - 8) >> 3] : 0u;
+      codes = cols;
+      return;
+    }
+  } else {
+    if ((lo & 7) == 0) {
+      const uint2 v = *reinterpret_cast<const uint2*>(a.bases + lo - 8);
+      const uint32_t x[2] = {v.x, v.y};
+      cols = codes = rst = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t b = (x[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+        const uint32_t t = (b >> 1) & 3u;
+        const uint32_t expect = (0x47544341u >> (8u * t)) & 0xFFu;
+        if ((b & 0xDFu) != expect) rst |= 1u << i;
+        cols |= t << (2 * i);
+        codes |= (t ^ (t >> 1)) << (2 * i);
+      }
+      return;
+    }
+  }
+  cols = codes = rst = 0;
+  for (int i = 0; i < 8; ++i) {
+    const int col = load_col<ENC>(a, lo - 8 + i);
+    if (col < 0) rst |= 1u << i;
+    else {
+      cols |= (uint32_t)col << (2 * i);
+      codes |= col_to_code<ENC>((uint32_t)col) << (2 * i);
+    }
+  }
+}
+
+// Candidate list of the chunk starting at lo: either one exact state (chunk
+// 0, a reset inside the lookback window, or a window that reaches the
+// sequence start) or the PSS table entry of the k-gram before the chunk.
 template <int ENC, int SHIFT>
-__device__ __forceinline__ void chunk_header(const ScanArgs& a, const Tab& tb, uint64_t lo, uint32_t& m, uint32_t& cbase,
-                             uint32_t& exact, bool& is_exact) {
+__device__ __forceinline__ void chunk_header(const ScanArgs& a, const Tab& tb, const uint32_t* pss_off, uint64_t lo,
+                                             uint32_t& m, uint32_t& cbase, uint32_t& exact, bool& is_exact) {
   m = 1;
   cbase = 0;
   exact = tb.q0s;
   is_exact = true;
   if (lo == 0) return;
-  const uint64_t k = a.k;
-  const uint64_t kk = lo < k ? lo : k;
-  bool reset = false;
-  uint32_t idx = 0;
-  for (uint64_t i = 0; i < kk; ++i) {
-    int col = load_col<ENC>(a, lo - kk + i);
-    if (col < 0) reset = true;
-    else idx |= col_to_code<ENC>((uint32_t)col) << (2 * i);
-  }
-  if (reset || kk < k) {
+  const uint32_t k = a.k;
+  if (lo < 8) {  // the window reaches the sequence start: run from q0
     uint32_t s = tb.q0s;
-    for (uint64_t i = 0; i < kk; ++i) {
-      int col = load_col<ENC>(a, lo - kk + i);
+    for (uint64_t i = 0; i < lo; ++i) {
+      const int col = load_col<ENC>(a, i);
       s = col < 0 ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (uint32_t)col) & 0xFFFFu);
     }
     exact = s;
     return;
   }
+  uint32_t cols, codes, rst;
+  lookback8<ENC>(a, lo, cols, codes, rst);
+  const uint32_t sh = 8 - k;  // window = the last k of the 8 bases
+  const uint32_t wr = (rst >> sh) & ((1u << k) - 1u);
+  if (wr) {  // a reset inside the window: the state is exact after it
+    uint32_t s = tb.q0s;
+    for (uint32_t i = sh; i < 8; ++i)
+      s = ((rst >> i) & 1u) ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (cols >> (2 * i)) & 3u) & 0xFFFFu);
+    exact = s;
+    return;
+  }
+  const uint32_t idx = (codes >> (2 * sh)) & ((k == 16 ? 0u : (1u << (2 * k))) - 1u);
   is_exact = false;
-  cbase = a.pss_off[idx];
-  m = a.pss_off[idx + 1] - cbase;
+  cbase = pss_off[idx];
+  m = pss_off[idx + 1] - cbase;
 }
 
-// The first SPEC_WIN symbols of [lo, hi): columns two bits per base (base i
-// at bits 2i of the 128-bit pair sy0:sy1) and a reset bit per base (rs).
+// First SPEC_WIN symbols of [lo, hi) for block-unaligned chunk starts
+// (aligned starts take them from the chunk's first block).
 template <int ENC>
-__device__ __forceinline__ void stage_symbols(const ScanArgs& a, uint64_t lo, uint64_t hi, uint64_t& sy0, uint64_t& sy1,
-                              uint64_t& rs) {
+__device__ __forceinline__ void stage_symbols(const ScanArgs& a, uint64_t lo, uint64_t hi, uint64_t& sy0,
+                                              uint64_t& sy1, uint64_t& rs) {
   uint32_t c[4] = {0, 0, 0, 0}, r[4] = {0, 0, 0, 0};
-  if ((lo & 15) == 0 && lo + SPEC_WIN <= hi) {
-#pragma unroll
-    for (int w = 0; w < 4; ++w) load_word<ENC>(a, lo + 16 * w, c[w], r[w]);
-  } else {
-    for (uint32_t i = 0; i < SPEC_WIN && lo + i < hi; ++i) {
-      const int col = load_col<ENC>(a, lo + i);
-      const uint32_t bit = col < 0 ? 0u : (uint32_t)col;
-      // i / 16 selects the word; written without indexing a register array
-      const uint32_t w = i >> 4, sh = 2 * (i & 15), rb = col < 0 ? 1u << (i & 15) : 0u;
-      c[0] |= w == 0 ? bit << sh : 0u;
-      c[1] |= w == 1 ? bit << sh : 0u;
-      c[2] |= w == 2 ? bit << sh : 0u;
-      c[3] |= w == 3 ? bit << sh : 0u;
-      r[0] |= w == 0 ? rb : 0u;
-      r[1] |= w == 1 ? rb : 0u;
-      r[2] |= w == 2 ? rb : 0u;
-      r[3] |= w == 3 ? rb : 0u;
-    }
+  for (uint32_t i = 0; i < SPEC_WIN && lo + i < hi; ++i) {
+    const int col = load_col<ENC>(a, lo + i);
+    const uint32_t bit = col < 0 ? 0u : (uint32_t)col;
+    const uint32_t w = i >> 4, sh = 2 * (i & 15), rb = col < 0 ? 1u << (i & 15) : 0u;
+    c[0] |= w == 0 ? bit << sh : 0u;
+    c[1] |= w == 1 ? bit << sh : 0u;
+    c[2] |= w == 2 ? bit << sh : 0u;
+    c[3] |= w == 3 ? bit << sh : 0u;
+    r[0] |= w == 0 ? rb : 0u;
+    r[1] |= w == 1 ? rb : 0u;
+    r[2] |= w == 2 ? rb : 0u;
+    r[3] |= w == 3 ? rb : 0u;
   }
   sy0 = (uint64_t)c[0] | ((uint64_t)c[1] << 32);
   sy1 = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
   rs = (uint64_t)r[0] | ((uint64_t)r[1] << 16) | ((uint64_t)r[2] << 32) | ((uint64_t)r[3] << 48);
 }
 
-template <int ENC, int SHIFT, int STEP, class Sink>
-__device__ __forceinline__ void tile(const ScanArgs& a, const Tab& tb, uint64_t tile_id, Sink& sink_proto) {
+// First SPEC_WIN symbols of a chunk starting at lo with lo % 64 == 0 and
+// lo + 64 <= n: one 16-byte load of codes and one 8-byte load of N bits
+// (2-bit), or four 16-byte loads (bytes).
+template <int ENC>
+__device__ __forceinline__ void front_symbols(const ScanArgs& a, uint64_t lo, uint64_t& sy0, uint64_t& sy1,
+                                              uint64_t& rs) {
+  if constexpr (ENC == ENC_2BIT) {
+    const uint4 v = *reinterpret_cast<const uint4*>(a.bases + (lo >> 2));
+    sy0 = (uint64_t)v.x | ((uint64_t)v.y << 32);
+    sy1 = (uint64_t)v.z | ((uint64_t)v.w << 32);
+    if (a.nmask) {
+      const uint2 mm = *reinterpret_cast<const uint2*>(a.nmask + (lo >> 3));
+      rs = (uint64_t)mm.x | ((uint64_t)mm.y << 32);
+    } else {
+      rs = 0;
+    }
+  } else {
+    Block<ENC_BYTE> b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b.r[i] = *reinterpret_cast<const uint4*>(a.bases + lo + 16 * i);
+    uint32_t c[4], r[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) b.word(w, c[w], r[w]);
+    sy0 = (uint64_t)c[0] | ((uint64_t)c[1] << 32);
+    sy1 = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
+    rs = (uint64_t)r[0] | ((uint64_t)r[1] << 16) | ((uint64_t)r[2] << 32) | ((uint64_t)r[3] << 48);
+  }
+}
+
+// Runs `count` (<= SPEC_WIN) staged symbols from s.
+template <int SHIFT, class Sink>
+__device__ __forceinline__ uint32_t run_staged(const Tab& tb, uint32_t s, uint64_t sy0, uint64_t sy1, uint64_t rs,
+                                               uint32_t count, uint64_t p, Sink& sink) {
+  for (uint32_t t = 0; t < count; ++t) {
+    const int col = (rs & 1u) ? -1 : (int)(sy0 & 3u);
+    s = step1<SHIFT>(tb, s, col, p + t, sink);
+    sy0 = (sy0 >> 2) | (sy1 << 62);
+    sy1 >>= 2;
+    rs >>= 1;
+  }
+  return s;
+}
+
+// Speculation for one tile of 64 chunks (one wave): possible starting states
+// from the lookback table, then rounds in which G lanes run the candidates
+// of one chunk in lockstep over its first symbols until they agree (the
+// converging point of Algorithm 1).  Writes conv_t / conv_s per chunk, or
+// queues the chunk as non-converged.
+template <int ENC, int SHIFT>
+__device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, const uint32_t* pss_off,
+                                          const uint16_t* pss_states, uint64_t tile_id) {
   const int lane = threadIdx.x & 63;
   const uint64_t c = tile_id * TILE + lane;
   const bool valid = c < a.n_chunks;
   const uint64_t lo = valid ? c * a.chunk : 0;
   const uint64_t hi = valid ? (lo + a.chunk < a.n ? lo + a.chunk : a.n) : 0;
-
-  // ---- this lane's chunk: candidates and its first SPEC_WIN symbols
   uint32_t m = 0, cbase = 0, exact = 0;
   bool is_exact = false;
-  if (valid) chunk_header<ENC, SHIFT>(a, tb, lo, m, cbase, exact, is_exact);
   uint64_t sy0 = 0, sy1 = 0, rs = 0;
-  if (valid) stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
+  if (valid) {
+    if ((lo & 63) == 0 && lo + SPEC_WIN <= a.n) front_symbols<ENC>(a, lo, sy0, sy1, rs);
+    else stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
+    chunk_header<ENC, SHIFT>(a, tb, pss_off, lo, m, cbase, exact, is_exact);
+  }
   const uint32_t len = (uint32_t)((hi - lo) < SPEC_WIN ? (hi - lo) : SPEC_WIN);
-
-  // ---- speculation: rounds of 64/G chunks, G lanes per chunk
   const uint32_t G = a.group;
   const uint32_t R = 64u / G;
   const uint32_t gidx = lane / G, gi = lane % G, gl = lane & ~(G - 1);
@@ -152,9 +242,8 @@ __device__ __forceinline__ void tile(const ScanArgs& a, const Tab& tb, uint64_t 
     uint64_t o0 = __shfl(sy0, owner), o1 = __shfl(sy1, owner), orr = __shfl(rs, owner);
     const bool act = om > 0 && om <= G;
     uint32_t s = tb.q0s;
-    if (act) s = oisx ? oex : ((uint32_t)a.pss_states[ocb + (gi < om ? gi : om - 1)] << SHIFT);
+    if (act) s = oisx ? oex : ((uint32_t)pss_states[ocb + (gi < om ? gi : om - 1)] << SHIFT);
     uint32_t res_t = NONCONV, res_s = 0;
-    // check after t symbols, then read symbol t; the symbol window shifts down
     for (uint32_t t = 0; t <= (uint32_t)SPEC_WIN; ++t) {
       const uint32_t lead = __shfl(s, (int)gl);
       const unsigned long long ne = __ballot(act && s != lead);
@@ -168,7 +257,6 @@ __device__ __forceinline__ void tile(const ScanArgs& a, const Tab& tb, uint64_t 
       o1 >>= 2;
       orr >>= 1;
     }
-    // hand the result to the chunk's owner lane
     const int src = (int)(((uint32_t)lane - r * R) * G) & 63;
     const uint32_t rt = __shfl(res_t, src);
     const uint32_t rv = __shfl(res_s, src);
@@ -177,30 +265,46 @@ __device__ __forceinline__ void tile(const ScanArgs& a, const Tab& tb, uint64_t 
       my_s = rv;
     }
   }
-
-  // ---- the rest of the chunk from the converging point
   if (!valid) return;
-  uint32_t out_e = 0, out_cnt = 0;
-  if (my_t != NONCONV) {
-    Sink sink = sink_proto;
-    sink.cnt = 0;
-    out_e = scan_range<ENC, SHIFT, STEP>(a, tb, my_s, lo + my_t, hi, sink);
-    out_cnt = sink.cnt;
-  } else {
+  if (my_t == NONCONV) {
     const uint32_t slot = atomicAdd(a.nc_count, 1u);
     a.nc_chunk[slot] = (uint32_t)c;
     a.nc_slot[c] = slot;
   }
   a.conv_t[c] = my_t;
   a.conv_s[c] = my_s;
-  a.end_s[c] = out_e;
-  a.tail_cnt[c] = out_cnt;
 }
 
+// LDS: one-symbol table, then the PSS table when it fits.
+template <int ENC, int SHIFT>
+__global__ __launch_bounds__(256) void k_spec(ScanArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  copy_to_lds(lds, a.T1, a.n_states * 16u);
+  const uint32_t* pss_off = a.pss_off;
+  const uint16_t* pss_states = a.pss_states;
+  if (a.spec_pss_off) {
+    uint32_t* po = reinterpret_cast<uint32_t*>(lds + a.spec_pss_off);
+    uint16_t* ps = reinterpret_cast<uint16_t*>(lds + a.spec_pss_states);
+    for (uint32_t i = threadIdx.x; i < a.pss_n_off; i += blockDim.x) po[i] = a.pss_off[i];
+    for (uint32_t i = threadIdx.x; i < a.pss_n_states; i += blockDim.x) ps[i] = a.pss_states[i];
+    pss_off = po;
+    pss_states = ps;
+  }
+  __syncthreads();
+  const Tab tb{nullptr, lds, a.q0s};
+  const uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (t < a.n_tiles) spec_tile<ENC, SHIFT>(a, tb, pss_off, pss_states, t);
+}
+
+// The scan of each chunk from its converging point (one lane per chunk),
+// then the join inside the wave: the predecessor lane's last state is this
+// chunk's true first state, from which the prefix before the converging
+// point is recounted.  The first lane of a wave, non-converged chunks and
+// their successors are left to the fix-up kernel.
 // HIST: per-final-state visit histogram in LDS (several patterns); else a
 // total with exact two-symbol counts.
 template <int ENC, int SHIFT, int STEP, bool HIST>
-__global__ __launch_bounds__(kScanBlock) void k_spec_tail(ScanArgs a) {
+__global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX_TAIL_WAVES, 8))) void k_tail(ScanArgs a) {
   extern __shared__ __align__(16) char lds[];
   if (STEP == 2) copy_to_lds(lds, a.T2, a.n_states * 64u);
   copy_to_lds(lds + a.lds_t1_off, a.T1, a.n_states * 16u);
@@ -211,16 +315,54 @@ __global__ __launch_bounds__(kScanBlock) void k_spec_tail(ScanArgs a) {
     if (HIST) hist[i] = 0;
   }
   __syncthreads();
-  Tab tb{lds, lds + a.lds_t1_off, a.q0s};
-  const uint64_t wpb = blockDim.x >> 6;
-  const uint64_t wave = threadIdx.x >> 6;
-  if constexpr (HIST) {
-    SinkHist proto{wl, hist};
-    for (uint64_t t = blockIdx.x * wpb + wave; t < a.n_tiles; t += gridDim.x * wpb) tile<ENC, SHIFT, STEP>(a, tb, t, proto);
-  } else {
-    SinkTotal proto{wl};
-    for (uint64_t t = blockIdx.x * wpb + wave; t < a.n_tiles; t += gridDim.x * wpb) tile<ENC, SHIFT, STEP>(a, tb, t, proto);
+  const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
+  using Sink = typename std::conditional<HIST, SinkHist, SinkTotal>::type;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = c < a.n_chunks;
+  uint32_t my_t = NONCONV, my_s = 0;
+  if (valid) {
+    my_t = a.conv_t[c];
+    my_s = a.conv_s[c];
   }
+  const bool conv = my_t != NONCONV;
+  const uint64_t lo = c * a.chunk;
+  uint32_t out_e = 0, out_cnt = 0;
+  if (conv) {
+    const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+    Sink sink;
+    if constexpr (HIST) sink = SinkHist{wl, hist};
+    else sink = SinkTotal{wl};
+    out_e = scan_range<ENC, SHIFT, STEP>(a, tb, my_s, lo + my_t, hi, sink);
+    out_cnt = sink.cnt;
+  }
+  const uint32_t pe = __shfl_up(out_e, 1u);
+  const int pconv = __shfl_up((int)conv, 1u);
+  uint64_t fixed_total = 0;
+  bool fixed = false;
+  if (conv && lane > 0 && pconv) {
+    const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+    Sink sink;
+    if constexpr (HIST) sink = SinkHist{wl, hist};
+    else sink = SinkTotal{wl};
+    uint64_t sy0, sy1, rs;
+    if ((lo & 63) == 0 && lo + SPEC_WIN <= a.n) front_symbols<ENC>(a, lo, sy0, sy1, rs);
+    else stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
+    const uint32_t e = run_staged<SHIFT>(tb, pe, sy0, sy1, rs, my_t, lo, sink);
+    if (e != my_s) atomicOr(a.err, 32u);
+    out_cnt += sink.cnt;
+    fixed = true;
+    fixed_total = out_cnt;
+  }
+  if (valid) {
+    if (!fixed) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)c;
+    else if (a.chunk_cnt) a.chunk_cnt[c] = out_cnt;
+    if (fixed) a.conv_t[c] = my_t | FIXED;
+    a.end_s[c] = out_e;
+    a.tail_cnt[c] = out_cnt;
+  }
+  for (int o = 32; o > 0; o >>= 1) fixed_total += __shfl_down(fixed_total, o);
+  if (lane == 0 && fixed_total) atomicAdd(a.total, (unsigned long long)fixed_total);
   if constexpr (HIST) {
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x)
@@ -242,7 +384,7 @@ __global__ __launch_bounds__(256) void k_nonconv(ScanArgs a) {
     const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     uint32_t m, cbase, exact;
     bool is_exact;
-    chunk_header<ENC, SHIFT>(a, tb, lo, m, cbase, exact, is_exact);
+    chunk_header<ENC, SHIFT>(a, tb, a.pss_off, lo, m, cbase, exact, is_exact);
     if (lane == 0) a.nc_m[slot] = m;
     for (uint32_t b = 0; b < m; b += 64) {
       const uint32_t i = b + lane;
@@ -284,33 +426,38 @@ __global__ void k_compose(ScanArgs a) {
   }
 }
 
-// Count fix-up: recount the chunk prefix before the converging point from the
-// true first state (whole chunk if it did not converge); check the run lands
-// on the converged state; per-chunk totals and the global total.
+// Count fix-up for the chunks the scan kernel could not join inside a wave
+// (first lane of a tile, non-converged chunks and their successors):
+// recount the prefix before the converging point from the true first state
+// (the whole chunk if it did not converge), check the run lands on the
+// converged state, and add the chunk's total.
 template <int ENC, int SHIFT, int STEP>
 __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state) {
-  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t mine = 0;
-  if (c < a.n_chunks) {
-    const Tab tb{reinterpret_cast<const char*>(a.T2), reinterpret_cast<const char*>(a.T1), a.q0s};
+  const Tab tb{reinterpret_cast<const char*>(a.T2), reinterpret_cast<const char*>(a.T1), a.q0s};
+  const uint32_t n_fix = *a.fix_count;
+  uint64_t mine_sum = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_fix; i += gridDim.x * blockDim.x) {
+    const uint64_t c = a.fix_list[i];
     const uint64_t lo = c * a.chunk;
     const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     SinkGlobal sink{a.wtab, per_state ? a.visits : nullptr};
     const uint32_t s0 = a.true_start[c];
-    if (a.conv_t[c] == NONCONV) {
+    uint64_t mine;
+    const uint32_t ct = a.conv_t[c];
+    if (ct == NONCONV) {
       const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
       if (e != a.true_start[c + 1]) atomicOr(a.err, 2u);
       mine = sink.cnt;
     } else {
-      const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, lo + a.conv_t[c], sink);
+      const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, lo + ct, sink);
       if (e != a.conv_s[c]) atomicOr(a.err, 4u);
       mine = (uint64_t)sink.cnt + a.tail_cnt[c];
     }
     if (a.chunk_cnt) a.chunk_cnt[c] = mine;
+    mine_sum += mine;
   }
-  // wave sum, one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o);
-  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(a.total, (unsigned long long)mine);
+  for (int o = 32; o > 0; o >>= 1) mine_sum += __shfl_down(mine_sum, o);
+  if ((threadIdx.x & 63) == 0 && mine_sum) atomicAdd(a.total, (unsigned long long)mine_sum);
 }
 
 // Per-pattern counts: totals for a one-pattern automaton, else visits of each
@@ -426,7 +573,11 @@ struct Workspace {
   char* buf = nullptr;
   size_t bytes = 0;
   int device = -1;
+  // event pairs around the scan kernel of calls made with COEX_FLAG_TIME
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t ev_used = 0;
 };
+constexpr size_t kMaxTimedLaunches = 4096;
 std::map<std::pair<int, void*>, Workspace> g_ws;  // (device, stream) -> workspace
 
 int dev_props(int dev, int& n_cu) {
@@ -537,9 +688,10 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
 }
 
 // Grow-only scratch per (device, stream).
-int workspace(int dev, void* stream, size_t bytes, char*& out) {
+int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) {
   std::lock_guard<std::mutex> lk(g_mu);
   Workspace& w = g_ws[{dev, stream}];
+  wsp = &w;
   if (w.bytes < bytes) {
     if (w.buf) {
       if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return COEX_EDEVICE;
@@ -557,7 +709,7 @@ int workspace(int dev, void* stream, size_t bytes, char*& out) {
 }
 
 struct Plan {
-  uint32_t shift, step, k, group, max_cand, blocks, lds_bytes;
+  uint32_t shift, step, k, group, max_cand, blocks, lds_bytes, spec_lds_bytes;
   uint64_t chunk, n_chunks, n_tiles;
   bool hist;
   int enc;
@@ -609,31 +761,51 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
   return COEX_OK;
 }
 
+// Events bracketing the scan kernel when the call asked for timing.
+std::pair<hipEvent_t, hipEvent_t>* timing_slot(Workspace* w) {
+  if (!w || w->ev_used >= kMaxTimedLaunches) return nullptr;
+  if (w->ev_used == w->ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return nullptr;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return nullptr; }
+    w->ev.push_back({a, b});
+  }
+  return &w->ev[w->ev_used++];
+}
+
 template <int ENC, int SHIFT, int STEP, bool HIST>
-void launch_spec(const Plan& P, const ScanArgs& a, int n_cu, hipStream_t st) {
-  auto kern = k_spec_tail<ENC, SHIFT, STEP, HIST>;
-  (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
-  const uint64_t want = (P.n_tiles + (kScanBlock / 64) - 1) / (kScanBlock / 64);
-  const uint32_t per_cu = P.lds_bytes <= 80 * 1024 ? 2 : 1;
-  const uint64_t cap = (uint64_t)n_cu * per_cu;
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kScanBlock), P.lds_bytes, st, a);
+void launch_scan(const Plan& P, const ScanArgs& a, int n_cu, hipStream_t st, Workspace* timed) {
+  (void)n_cu;
+  // speculation: one wave per tile, 4 tiles per 256-thread block
+  const uint32_t spec_blocks = (uint32_t)std::max<uint64_t>(1, (P.n_tiles + 3) / 4);
+  auto ks = k_spec<ENC, SHIFT>;
+  (void)hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.spec_lds_bytes);
+  hipLaunchKernelGGL(ks, dim3(spec_blocks), dim3(256), P.spec_lds_bytes, st, a);
+  // scan from the converging points: one lane per chunk
+  auto kt = k_tail<ENC, SHIFT, STEP, HIST>;
+  (void)hipFuncSetAttribute((const void*)kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (P.n_chunks + kScanBlock - 1) / kScanBlock);
+  auto* ev = timed ? timing_slot(timed) : nullptr;
+  if (ev) (void)hipEventRecord(ev->first, st);
+  hipLaunchKernelGGL(kt, dim3(blocks), dim3(kScanBlock), P.lds_bytes, st, a);
+  if (ev) (void)hipEventRecord(ev->second, st);
 }
 
 template <int ENC, int SHIFT, int STEP>
-void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint64_t* counts, bool emit_counts) {
+void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint64_t* counts, bool emit_counts,
+                     Workspace* timed) {
   hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, a, counts, emit_counts ? a.n_patterns : 0u);
   if (P.n_chunks == 0) {
     if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
     return;
   }
-  if (P.hist) launch_spec<ENC, SHIFT, STEP, true>(P, a, n_cu, st);
-  else launch_spec<ENC, SHIFT, STEP, false>(P, a, n_cu, st);
+  if (P.hist) launch_scan<ENC, SHIFT, STEP, true>(P, a, n_cu, st, timed);
+  else launch_scan<ENC, SHIFT, STEP, false>(P, a, n_cu, st, timed);
   constexpr int DSTEP = SHIFT == 6 ? 2 : 1;  // global-table kernels always use the widest step
   hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), 0, st, a);
   const uint32_t cb = (uint32_t)((P.n_chunks + 1 + 255) / 256);
   hipLaunchKernelGGL(k_compose, dim3(cb), dim3(256), 0, st, a);
-  const uint32_t fb = (uint32_t)((P.n_chunks + 255) / 256);
+  const uint32_t fb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P.n_chunks + 255) / 256, n_cu));
   hipLaunchKernelGGL((k_fixup<ENC, SHIFT, DSTEP>), dim3(fb), dim3(256), 0, st, a, (int)P.hist);
   if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
 }
@@ -641,6 +813,8 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
 // Everything a scan call shares: validation, upload, plan, workspace, args.
 struct Call {
   int dev = 0, n_cu = 0;
+  Workspace* wsp = nullptr;
+  bool timed = false;
   DeviceCopy* dc = nullptr;
   Plan P{};
   ScanArgs a{};
@@ -671,19 +845,35 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   const uint32_t t1_off = P.step == 2 ? n * 64 : 0;
   const uint32_t w_off = t1_off + n * 16;
   const uint32_t h_off = w_off + (uint32_t)align_up(d.n_accepting * 4, 16);
-  P.lds_bytes = h_off + (uint32_t)align_up(d.n_accepting * 4, 16) + 16;
+  uint32_t lds_end = h_off + (uint32_t)align_up(d.n_accepting * 4, 16);
+  // the PSS table of the chosen lookback goes to LDS when it is small
+  const uint32_t pss_n_off = (uint32_t)d.pss[P.k].off.size();
+  const uint32_t pss_n_st = (uint32_t)d.pss[P.k].states.size();
+  const uint32_t pss_bytes = (uint32_t)align_up(pss_n_off * 4, 16) + (uint32_t)align_up(pss_n_st * 2, 16);
+  P.lds_bytes = lds_end + 16;
+  uint32_t spec_pss_off = 0, spec_pss_states = 0;
+  const uint32_t spec_t1 = n * 16;
+  if (pss_bytes <= 48 * 1024) {
+    spec_pss_off = spec_t1;
+    spec_pss_states = spec_t1 + (uint32_t)align_up(pss_n_off * 4, 16);
+    P.spec_lds_bytes = spec_t1 + pss_bytes + 16;
+  } else {
+    P.spec_lds_bytes = spec_t1 + 16;
+  }
   // workspace layout
   const uint64_t nc = P.n_chunks;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off = align_up(off + std::max<size_t>(bytes, 8), 256); return o2; };
   size_t o_ct = take(nc * 4), o_cs = take(nc * 4), o_es = take(nc * 4), o_tc = take(nc * 4);
   size_t o_ncc = take(4), o_nch = take(nc * 4), o_nsl = take(nc * 4), o_nm = take(nc * 4);
+  size_t o_fxc = take(4), o_fxl = take(nc * 4);
   size_t o_nca = take(nc * P.max_cand * 4), o_nen = take(nc * P.max_cand * 4);
   size_t o_ts = take((nc + 1) * 4), o_vis = take((size_t)d.n_accepting * 8), o_tot = take(8), o_err = take(4);
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
-  rc = workspace(C.dev, stream, off, C.ws);
+  rc = workspace(C.dev, stream, off, C.ws, C.wsp);
   if (rc) return rc;
   C.st = (hipStream_t)stream;
+  C.timed = o && (o->flags & COEX_FLAG_TIME);
   ScanArgs& a = C.a;
   char* w = C.ws;
   a.bases = reinterpret_cast<const uint8_t*>(seq->bases);
@@ -712,6 +902,12 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.end_s = reinterpret_cast<uint32_t*>(w + o_es);
   a.tail_cnt = reinterpret_cast<uint32_t*>(w + o_tc);
   a.nc_count = reinterpret_cast<uint32_t*>(w + o_ncc);
+  a.fix_count = reinterpret_cast<uint32_t*>(w + o_fxc);
+  a.fix_list = reinterpret_cast<uint32_t*>(w + o_fxl);
+  a.spec_pss_off = spec_pss_off;
+  a.spec_pss_states = spec_pss_states;
+  a.pss_n_off = pss_n_off;
+  a.pss_n_states = pss_n_st;
   a.nc_chunk = reinterpret_cast<uint32_t*>(w + o_nch);
   a.nc_slot = reinterpret_cast<uint32_t*>(w + o_nsl);
   a.nc_m = reinterpret_cast<uint32_t*>(w + o_nm);
@@ -735,14 +931,14 @@ void run_pipeline(Call& C, uint64_t* counts, bool emit_counts) {
   const bool b = C.P.enc == 0;
   const Plan& P = C.P;
   if (P.shift == 6 && P.step == 2) {
-    if (b) launch_pipeline<ENC_BYTE, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts);
-    else launch_pipeline<ENC_2BIT, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+    if (b) launch_pipeline<ENC_BYTE, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
+    else launch_pipeline<ENC_2BIT, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
   } else if (P.shift == 6) {
-    if (b) launch_pipeline<ENC_BYTE, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
-    else launch_pipeline<ENC_2BIT, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+    if (b) launch_pipeline<ENC_BYTE, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
+    else launch_pipeline<ENC_2BIT, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
   } else {
-    if (b) launch_pipeline<ENC_BYTE, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
-    else launch_pipeline<ENC_2BIT, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts);
+    if (b) launch_pipeline<ENC_BYTE, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
+    else launch_pipeline<ENC_2BIT, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
   }
 }
 
@@ -964,6 +1160,30 @@ const char* coex_strerror(int s) {
     case COEX_EINTERNAL: return "device consistency check failed";
     default: return "unknown status";
   }
+}
+
+int coex_profile(void* stream, double* total_ms, uint64_t* launches, int reset) {
+  if (!total_ms || !launches) return COEX_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return COEX_EDEVICE;
+  std::lock_guard<std::mutex> lk(coex::g_mu);
+  auto it = coex::g_ws.find({dev, stream});
+  double sum = 0.0;
+  uint64_t cnt = 0;
+  if (it != coex::g_ws.end()) {
+    coex::Workspace& w = it->second;
+    for (size_t i = 0; i < w.ev_used; ++i) {
+      if (hipEventSynchronize(w.ev[i].second) != hipSuccess) return COEX_EDEVICE;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, w.ev[i].first, w.ev[i].second) != hipSuccess) return COEX_EDEVICE;
+      sum += ms;
+      ++cnt;
+    }
+    if (reset) w.ev_used = 0;
+  }
+  *total_ms = sum;
+  *launches = cnt;
+  return COEX_OK;
 }
 
 const char* coex_version(void) { return "coex 0.1 gfx950"; }

@@ -31,11 +31,32 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Double-buffer the middle blocks of a chunk scan (1) or load each block
+// just before scanning it (0).
+#ifndef COEX_PREFETCH
+#define COEX_PREFETCH 0
+#endif
+// Bases per register block of the 2-bit scan (256: 64 + 32 bytes per lane
+// and load round; 512: 128 + 64 bytes).
+#ifndef COEX_BLOCK2
+#define COEX_BLOCK2 512
+#endif
+// Threads per block of the scan kernels.
+#ifndef COEX_SCAN_BLOCK
+#define COEX_SCAN_BLOCK 768
+#endif
+// Minimum waves per SIMD the chunk-scan kernel is compiled for (caps its
+// registers at 512 / waves).
+#ifndef COEX_TAIL_WAVES
+#define COEX_TAIL_WAVES 6
+#endif
+
 namespace coex {
 
 constexpr int ENC_BYTE = 0;
 constexpr int ENC_2BIT = 1;
 constexpr uint32_t NONCONV = 0xFFFFFFFFu;
+constexpr uint32_t FIXED = 0x40000000u;   // conv_t flag: prefix already recounted in the scan kernel
 constexpr int TILE = 64;          // chunks per wave
 constexpr int SPEC_WIN = 64;      // symbols examined for convergence
 
@@ -68,6 +89,12 @@ struct ScanArgs {
   uint32_t* conv_s;           // state there
   uint32_t* end_s;            // state at the chunk end (converged chunks)
   uint32_t* tail_cnt;         // matches in [conv_t, end)
+  uint32_t* fix_count;        // chunks left for the fix-up kernel
+  uint32_t* fix_list;
+  uint32_t spec_pss_off;      // LDS byte offsets of the PSS table in the speculation kernel (0: not staged)
+  uint32_t spec_pss_states;
+  uint32_t pss_n_off;
+  uint32_t pss_n_states;
   uint32_t* nc_count;         // number of non-converged chunks
   uint32_t* nc_chunk;         // slot -> chunk
   uint32_t* nc_slot;          // chunk -> slot
@@ -247,124 +274,276 @@ __device__ __forceinline__ uint32_t step1(const Tab& tb, uint32_t s, int col, ui
   return e & 0xFFFFu;
 }
 
-// 16 symbols of one word, one at a time (resets honoured).
+// The bases of one 16-base word selected by `act` (bit i = base p+i), one
+// at a time, resets honoured.
 template <int SHIFT, class Sink>
-__device__ __forceinline__ uint32_t word_slow(const Tab& tb, uint32_t s, uint32_t cols, uint32_t rst, uint64_t p,
-                                              Sink& sink) {
+__device__ __forceinline__ uint32_t word_slow(const Tab& tb, uint32_t s, uint32_t cols, uint32_t rst, uint32_t act,
+                                              uint64_t p, Sink& sink) {
 #pragma unroll 1
   for (int i = 0; i < 16; ++i) {
+    if (!((act >> i) & 1u)) continue;
     int col = ((rst >> i) & 1u) ? -1 : (int)((cols >> (2 * i)) & 3u);
     s = step1<SHIFT>(tb, s, col, p + i, sink);
   }
   return s;
 }
 
-// 16 symbols without resets: eight two-symbol lookups (STEP 2), or sixteen
-// one-symbol lookups; a word with matches is replayed one symbol at a time
-// when the sink needs per-position detail.
-template <int SHIFT, int STEP, class Sink>
-__device__ __forceinline__ uint32_t word_fast(const Tab& tb, uint32_t s, uint32_t cols, uint64_t p, Sink& sink) {
+// 16 symbols without resets: eight two-symbol lookups (STEP 2) or sixteen
+// one-symbol lookups.  Returns the state after the word; `c` receives the
+// number of pattern ends in the word (STEP 2, exact two-symbol counts) or a
+// nonzero flag when any accepting state was visited.
+template <int SHIFT, int STEP>
+__device__ __forceinline__ uint32_t walk16(const Tab& tb, uint32_t s, uint32_t cols, uint32_t& c) {
   static_assert(STEP == 1 || SHIFT == 6, "two-symbol tables need 64-byte rows");
-  const uint32_t s0 = s;
+  uint32_t acc = 0;
   if constexpr (STEP == 2) {
-    uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       uint32_t e = t2_lookup(tb, s, (cols >> (4 * j)) & 15u);
       s = e & 0xFFFFu;
       acc += e;
     }
-    uint32_t c = acc >> 24;
-    if constexpr (Sink::kReplay) {
-      if (c) word_slow<SHIFT>(tb, s0, cols, 0u, p, sink);
-    } else {
-      sink.word(c);
-    }
+    c = acc >> 24;
   } else {
-    uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       uint32_t e = t1_lookup<SHIFT>(tb, s, (cols >> (2 * j)) & 3u);
       s = e & 0xFFFFu;
       acc |= e;
     }
-    if (acc >> 16) word_slow<SHIFT>(tb, s0, cols, 0u, p, sink);
+    c = acc >> 16;
   }
   return s;
 }
 
-// Scans [p, hi) from state s, reporting matches to the sink; returns the
-// state after base hi-1.  Single bases until p is 16-aligned, whole words
-// until the block boundary, whole blocks (128 bytes of sequence per lane and
-// load), then words and single bases again.
-template <int ENC, int SHIFT, int STEP, class Sink>
-__device__ __forceinline__ uint32_t scan_range(const ScanArgs& a, const Tab& tb, uint32_t s, uint64_t p, uint64_t hi, Sink& sink) {
-  constexpr uint64_t BLOCK = (ENC == ENC_2BIT) ? 512 : 128;
-  while (p < hi && (p & 15)) {
-    s = step1<SHIFT>(tb, s, load_col<ENC>(a, p), p, sink);
-    ++p;
+// One 16-base word with reset bits `rst`.  Words without resets and words
+// made only of resets (inside runs of N) take the table walk; the latter
+// end in q0 and report nothing, so lanes inside N runs do not diverge from
+// the others.  Words with a reset boundary go one base at a time.  A word
+// with matches is replayed base by base when the sink needs the detail (or
+// when the step cannot count exactly).
+template <int SHIFT, int STEP, class Sink>
+__device__ __forceinline__ uint32_t run_word(const Tab& tb, uint32_t s, uint32_t cols, uint32_t rst, uint64_t p,
+                                             Sink& sink) {
+  if (rst == 0u || rst == 0xFFFFu) {
+    uint32_t c;
+    uint32_t e = walk16<SHIFT, STEP>(tb, s, cols, c);
+    if (rst) {
+      e = tb.q0s;
+      c = 0;
+    }
+    if constexpr (Sink::kReplay || STEP == 1) {
+      if (c) word_slow<SHIFT>(tb, s, cols, 0u, 0xFFFFu, p, sink);
+    } else {
+      sink.word(c);
+    }
+    return e;
   }
-  while (p + 16 <= hi && (p & (BLOCK - 1))) {
-    uint32_t cols, rst;
-    load_word<ENC>(a, p, cols, rst);
-    s = rst ? word_slow<SHIFT>(tb, s, cols, rst, p, sink) : word_fast<SHIFT, STEP>(tb, s, cols, p, sink);
-    p += 16;
+  return word_slow<SHIFT>(tb, s, cols, rst, 0xFFFFu, p, sink);
+}
+
+// Kept for callers that know the word has no resets.
+template <int SHIFT, int STEP, class Sink>
+__device__ __forceinline__ uint32_t word_fast(const Tab& tb, uint32_t s, uint32_t cols, uint64_t p, Sink& sink) {
+  return run_word<SHIFT, STEP>(tb, s, cols, 0u, p, sink);
+}
+
+// A block of sequence held in registers: 512 bases (128 bytes of 2-bit codes
+// and 64 bytes of N mask) or 128 bases (128 bytes).  Loaded with 16-byte
+// loads per lane so each lane consumes whole 128-byte lines at once.
+template <int ENC>
+struct Block;
+
+template <>
+struct Block<ENC_2BIT> {
+  static constexpr uint64_t BASES = COEX_BLOCK2;
+  static constexpr int WORDS = (int)(BASES / 16);  // 16 bases per 32-bit word
+  static constexpr int MW = WORDS / 2;             // 32 bases per 32-bit mask word
+  uint32_t v[WORDS];
+  uint32_t m[MW];
+  __device__ __forceinline__ void word(int w, uint32_t& cols, uint32_t& rst) const {
+    cols = v[w];
+    rst = (m[w >> 1] >> (16 * (w & 1))) & 0xFFFFu;
   }
-  while (p + BLOCK <= hi) {
-    if constexpr (ENC == ENC_2BIT) {
-      const uint4* src = reinterpret_cast<const uint4*>(a.bases + (p >> 2));
-      uint4 v[8];
+  __device__ __forceinline__ uint32_t any_reset() const {
+    uint32_t x = 0;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = src[i];
-      uint4 m[4] = {};
-      uint32_t any = 0;
-      if (a.nmask) {
-        const uint4* ms = reinterpret_cast<const uint4*>(a.nmask + (p >> 3));
+    for (int i = 0; i < MW; ++i) x |= m[i];
+    return x;
+  }
+  // whole block inside the sequence
+  __device__ __forceinline__ void load(const ScanArgs& a, uint64_t base) {
+    const uint4* src = reinterpret_cast<const uint4*>(a.bases + (base >> 2));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          m[i] = ms[i];
-          any |= m[i].x | m[i].y | m[i].z | m[i].w;
-        }
-      }
-      const uint32_t vw[32] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w,
-                               v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w,
-                               v[4].x, v[4].y, v[4].z, v[4].w, v[5].x, v[5].y, v[5].z, v[5].w,
-                               v[6].x, v[6].y, v[6].z, v[6].w, v[7].x, v[7].y, v[7].z, v[7].w};
-      if (!any) {
+    for (int i = 0; i < WORDS / 4; ++i) {
+      uint4 t = src[i];
+      v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
+    }
+    if (a.nmask) {
+      const uint4* ms = reinterpret_cast<const uint4*>(a.nmask + (base >> 3));
 #pragma unroll
-        for (int w = 0; w < 32; ++w) s = word_fast<SHIFT, STEP>(tb, s, vw[w], p + 16 * w, sink);
-      } else {
-        const uint32_t mw[16] = {m[0].x, m[0].y, m[0].z, m[0].w, m[1].x, m[1].y, m[1].z, m[1].w,
-                                 m[2].x, m[2].y, m[2].z, m[2].w, m[3].x, m[3].y, m[3].z, m[3].w};
-#pragma unroll
-        for (int w = 0; w < 32; ++w) {
-          uint32_t r = (mw[w >> 1] >> (16 * (w & 1))) & 0xFFFFu;
-          s = r ? word_slow<SHIFT>(tb, s, vw[w], r, p + 16 * w, sink)
-                : word_fast<SHIFT, STEP>(tb, s, vw[w], p + 16 * w, sink);
-        }
+      for (int i = 0; i < MW / 4; ++i) {
+        uint4 t = ms[i];
+        m[4 * i] = t.x; m[4 * i + 1] = t.y; m[4 * i + 2] = t.z; m[4 * i + 3] = t.w;
       }
     } else {
-#pragma unroll 2
-      for (int w = 0; w < 8; ++w) {
-        uint32_t cols, rst;
-        load_word<ENC>(a, p + 16 * w, cols, rst);
-        s = rst ? word_slow<SHIFT>(tb, s, cols, rst, p + 16 * w, sink)
-                : word_fast<SHIFT, STEP>(tb, s, cols, p + 16 * w, sink);
+#pragma unroll
+      for (int i = 0; i < MW; ++i) m[i] = 0;
+    }
+  }
+  // block crossing the end of the sequence: only bytes below n are read
+  __device__ void load_partial(const ScanArgs& a, uint64_t base) {
+    const uint64_t nb = (a.n + 3) >> 2, nm = (a.n + 7) >> 3;
+#pragma unroll
+    for (int w = 0; w < WORDS; ++w) {
+      const uint64_t b = (base >> 2) + 4 * w;
+      uint32_t x = 0;
+      if (b + 4 <= nb) x = *reinterpret_cast<const uint32_t*>(a.bases + b);
+      else
+        for (uint64_t j = b; j < nb && j < b + 4; ++j) x |= (uint32_t)a.bases[j] << (8 * (j - b));
+      v[w] = x;
+    }
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+      const uint64_t b = (base >> 3) + 4 * i;
+      uint32_t x = 0;
+      if (a.nmask) {
+        if (b + 4 <= nm) x = *reinterpret_cast<const uint32_t*>(a.nmask + b);
+        else
+          for (uint64_t j = b; j < nm && j < b + 4; ++j) x |= (uint32_t)a.nmask[j] << (8 * (j - b));
+      }
+      m[i] = x;
+    }
+  }
+};
+
+template <>
+struct Block<ENC_BYTE> {
+  static constexpr uint64_t BASES = 128;
+  static constexpr int WORDS = 8;
+  uint4 r[8];
+  __device__ __forceinline__ void word(int w, uint32_t& cols, uint32_t& rst) const {
+    const uint32_t x[4] = {r[w].x, r[w].y, r[w].z, r[w].w};
+    cols = 0;
+    rst = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = (x[i] >> 1) & 0x03030303u;
+      const uint32_t expect = __builtin_amdgcn_perm(0u, 0x47544341u, t);  // 'A','C','T','G' by t
+      const uint32_t bad = (x[i] & 0xDFDFDFDFu) ^ expect;                 // nonzero byte: not ACGTacgt
+      const uint32_t u = t | (t >> 6);
+      cols |= ((u & 0xFu) | ((u >> 12) & 0xF0u)) << (8 * i);
+      uint32_t rb = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rb |= (((bad >> (8 * j)) & 0xFFu) != 0u) << j;
+      rst |= rb << (4 * i);
+    }
+  }
+  __device__ __forceinline__ uint32_t any_reset() const { return 1u; }  // checked per word
+  __device__ __forceinline__ void load(const ScanArgs& a, uint64_t base) {
+    const uint4* src = reinterpret_cast<const uint4*>(a.bases + base);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = src[i];
+  }
+  __device__ void load_partial(const ScanArgs& a, uint64_t base) {
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const uint64_t b = base + 16 * w;
+      if (b + 16 <= a.n) {
+        r[w] = *reinterpret_cast<const uint4*>(a.bases + b);
+      } else {
+        uint32_t x[4] = {0, 0, 0, 0};
+        for (uint64_t j = b; j < a.n && j < b + 16; ++j) x[(j - b) >> 2] |= (uint32_t)a.bases[j] << (8 * ((j - b) & 3));
+        r[w] = make_uint4(x[0], x[1], x[2], x[3]);
       }
     }
-    p += BLOCK;
   }
-  while (p + 16 <= hi) {
+};
+
+template <int ENC>
+__device__ __forceinline__ void load_block(const ScanArgs& a, uint64_t base, Block<ENC>& b) {
+  if (base + Block<ENC>::BASES <= a.n) b.load(a, base);
+  else b.load_partial(a, base);
+}
+
+// Runs the words of block `b` (first base `base`) that hold bases in
+// [lo, hi).  CHECKED = false promises the whole block lies in [lo, hi).
+template <int ENC, int SHIFT, int STEP, bool CHECKED, class Sink>
+__device__ __forceinline__ uint32_t run_block(const Tab& tb, uint32_t s, const Block<ENC>& b, uint64_t base,
+                                              uint64_t lo, uint64_t hi, Sink& sink) {
+  constexpr int W = Block<ENC>::WORDS;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
     uint32_t cols, rst;
-    load_word<ENC>(a, p, cols, rst);
-    s = rst ? word_slow<SHIFT>(tb, s, cols, rst, p, sink) : word_fast<SHIFT, STEP>(tb, s, cols, p, sink);
-    p += 16;
-  }
-  while (p < hi) {
-    s = step1<SHIFT>(tb, s, load_col<ENC>(a, p), p, sink);
-    ++p;
+    b.word(w, cols, rst);
+    const uint64_t p = base + 16 * w;
+    if (CHECKED) {
+      const uint64_t a0 = lo > p ? lo - p : 0;
+      const uint64_t a1 = hi < p + 16 ? (hi > p ? hi - p : 0) : 16;
+      if (a1 <= a0) continue;
+      const uint32_t act = (0xFFFFu >> (16 - a1)) & ~((1u << a0) - 1u);
+      if (act != 0xFFFFu) {
+        s = word_slow<SHIFT>(tb, s, cols, rst, act, p, sink);
+        continue;
+      }
+    }
+    s = run_word<SHIFT, STEP>(tb, s, cols, rst, p, sink);
   }
   return s;
+}
+
+// Scans [p, hi) from state s.  With HAS_FIRST, `first` already holds the
+// block containing p.  Middle blocks are double-buffered: the next block's
+// loads are in flight while the current one is scanned.
+template <int ENC, int SHIFT, int STEP, bool HAS_FIRST, class Sink>
+__device__ __forceinline__ uint32_t scan_blocks(const ScanArgs& a, const Tab& tb, uint32_t s, uint64_t p,
+                                                uint64_t hi, Sink& sink, const Block<ENC>& first) {
+  using B = Block<ENC>;
+  if (p >= hi) return s;
+  uint64_t base = p / B::BASES * B::BASES;
+  if constexpr (HAS_FIRST) {
+    s = run_block<ENC, SHIFT, STEP, true>(tb, s, first, base, p, hi, sink);
+  } else {
+    B blk;
+    load_block<ENC>(a, base, blk);
+    s = run_block<ENC, SHIFT, STEP, true>(tb, s, blk, base, p, hi, sink);
+  }
+  base += B::BASES;
+#if COEX_PREFETCH
+  if (base + B::BASES <= hi) {
+    B cur;
+    cur.load(a, base);
+    for (;;) {
+      const bool more = base + 2 * B::BASES <= hi;
+      B nxt;
+      if (more) nxt.load(a, base + B::BASES);
+      s = run_block<ENC, SHIFT, STEP, false>(tb, s, cur, base, base, base + B::BASES, sink);
+      base += B::BASES;
+      if (!more) break;
+      cur = nxt;
+    }
+  }
+#else
+  for (; base + B::BASES <= hi; base += B::BASES) {
+    B cur;
+    cur.load(a, base);
+    s = run_block<ENC, SHIFT, STEP, false>(tb, s, cur, base, base, base + B::BASES, sink);
+  }
+#endif
+  if (base < hi) {
+    B blk;
+    load_block<ENC>(a, base, blk);
+    s = run_block<ENC, SHIFT, STEP, true>(tb, s, blk, base, base, hi, sink);
+  }
+  return s;
+}
+
+// [p, hi) with every block loaded here.
+template <int ENC, int SHIFT, int STEP, class Sink>
+__device__ __forceinline__ uint32_t scan_range(const ScanArgs& a, const Tab& tb, uint32_t s, uint64_t p, uint64_t hi,
+                                               Sink& sink) {
+  Block<ENC> unused;
+  return scan_blocks<ENC, SHIFT, STEP, false>(a, tb, s, p, hi, sink, unused);
 }
 
 }  // namespace coex
