@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <type_traits>
 #include <cstdio>
 #include <cstdlib>
@@ -316,6 +317,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX
   }
   __syncthreads();
   const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
+  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
   using Sink = typename std::conditional<HIST, SinkHist, SinkTotal>::type;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -516,6 +518,7 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(ScanArgs a) {
   copy_to_lds(lds + a.lds_t1_off, a.T1, a.n_states * 16u);
   __syncthreads();
   const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
+  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n_chunks) return;
   const uint64_t lo = c * a.chunk;
@@ -715,6 +718,48 @@ struct Plan {
   int enc;
 };
 
+// Bytes of LDS the chunk-scan kernel stages: two-symbol table (step 2),
+// one-symbol table, weights and histogram.
+uint32_t tail_lds_bytes(uint32_t step, const Dfa& d) {
+  const uint32_t n = d.n_states;
+  const uint32_t acc = (uint32_t)align_up(d.n_accepting * 4, 16);
+  return (step == 2 ? n * 64 : 0) + n * 16 + 2 * acc + 16;
+}
+
+template <int ENC, int SHIFT, int STEP, bool HIST>
+int occupancy_of(uint32_t lds) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_tail<ENC, SHIFT, STEP, HIST>, kScanBlock, lds) !=
+      hipSuccess)
+    return 1;
+  return std::max(1, blocks);
+}
+
+// Resident blocks per CU of the chunk-scan kernel the plan will launch.
+uint32_t tail_blocks_per_cu(const Plan& P, const Dfa& d) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, uint32_t, uint32_t, bool, uint32_t>, int> cache;
+  const uint32_t lds = tail_lds_bytes(P.step, d);
+  const auto key = std::make_tuple(P.enc, P.shift, P.step, P.hist, lds);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return (uint32_t)it->second;
+  int b = 1;
+  const bool by = P.enc == 0;
+  if (P.shift == 6 && P.step == 2) {
+    if (by) b = P.hist ? occupancy_of<ENC_BYTE, 6, 2, true>(lds) : occupancy_of<ENC_BYTE, 6, 2, false>(lds);
+    else b = P.hist ? occupancy_of<ENC_2BIT, 6, 2, true>(lds) : occupancy_of<ENC_2BIT, 6, 2, false>(lds);
+  } else if (P.shift == 6) {
+    if (by) b = P.hist ? occupancy_of<ENC_BYTE, 6, 1, true>(lds) : occupancy_of<ENC_BYTE, 6, 1, false>(lds);
+    else b = P.hist ? occupancy_of<ENC_2BIT, 6, 1, true>(lds) : occupancy_of<ENC_2BIT, 6, 1, false>(lds);
+  } else {
+    if (by) b = P.hist ? occupancy_of<ENC_BYTE, 4, 1, true>(lds) : occupancy_of<ENC_BYTE, 4, 1, false>(lds);
+    else b = P.hist ? occupancy_of<ENC_2BIT, 4, 1, true>(lds) : occupancy_of<ENC_2BIT, 4, 1, false>(lds);
+  }
+  cache[key] = b;
+  return (uint32_t)b;
+}
+
 int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex_opts* o, int n_cu, Plan& P,
               bool force_hist) {
   P.enc = sq.encoding == COEX_ENC_2BIT ? 1 : 0;
@@ -745,11 +790,15 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
     P.group = g;
   }
   const uint64_t n = sq.n_bases;
+  P.hist = force_hist || d.n_patterns > 1 || (P.step == 2 && !dc.t2_exact);
   if (o && o->chunk) {
     P.chunk = o->chunk;
   } else {
-    const uint64_t lanes = (uint64_t)n_cu * 2048;
-    uint64_t c = (n + lanes - 1) / lanes;
+    // one round of the chunk-scan kernel over the whole GPU: as many chunks
+    // as lanes that can be resident at once (occupancy of the actual kernel
+    // with its LDS), chunk length a multiple of 512 bases
+    const uint64_t lanes = (uint64_t)n_cu * tail_blocks_per_cu(P, d) * kScanBlock;
+    uint64_t c = (n + lanes - 1) / std::max<uint64_t>(1, lanes);
     c = std::max<uint64_t>(512, align_up(c, 512));
     // bound the non-converged scratch (chunks * candidates * 8 bytes) to 512 MiB
     while ((n / c + 1) * (uint64_t)mx * 8 > (512ull << 20)) c *= 2;
@@ -757,7 +806,6 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
   }
   P.n_chunks = n == 0 ? 0 : (n + P.chunk - 1) / P.chunk;
   P.n_tiles = (P.n_chunks + TILE - 1) / TILE;
-  P.hist = force_hist || d.n_patterns > 1 || (P.step == 2 && !dc.t2_exact);
   return COEX_OK;
 }
 
@@ -801,7 +849,7 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
   }
   if (P.hist) launch_scan<ENC, SHIFT, STEP, true>(P, a, n_cu, st, timed);
   else launch_scan<ENC, SHIFT, STEP, false>(P, a, n_cu, st, timed);
-  constexpr int DSTEP = SHIFT == 6 ? 2 : 1;  // global-table kernels always use the widest step
+  constexpr int DSTEP = 1;  // kernels with global tables: one-symbol lookups (the two-symbol walk reads LDS)
   hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), 0, st, a);
   const uint32_t cb = (uint32_t)((P.n_chunks + 1 + 255) / 256);
   hipLaunchKernelGGL(k_compose, dim3(cb), dim3(256), 0, st, a);

@@ -288,23 +288,58 @@ __device__ __forceinline__ uint32_t word_slow(const Tab& tb, uint32_t s, uint32_
   return s;
 }
 
-// 16 symbols without resets: eight two-symbol lookups (STEP 2) or sixteen
-// one-symbol lookups.  Returns the state after the word; `c` receives the
-// number of pattern ends in the word (STEP 2, exact two-symbol counts) or a
-// nonzero flag when any accepting state was visited.
+// LDS read at a byte address.  The two-symbol table is staged at LDS
+// address 0 (the kernels using it declare no other LDS), so a state value
+// (row byte offset) plus a column offset is a complete LDS address.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+typedef __attribute__((address_space(3))) const char lds_c;
+__device__ __forceinline__ uint32_t lds_at(uint32_t addr) { return *(lds_u32*)(uintptr_t)addr; }
+
+// (e & 0xFFFF) + byte B of x in one VALU instruction (sub-dword operand
+// selection): the next row offset from a table entry plus a column offset.
+template <int B>
+__device__ __forceinline__ uint32_t row_plus_byte(uint32_t e, uint32_t x) {
+  uint32_t r;
+  if constexpr (B == 0)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_0"
+        : "=v"(r) : "v"(e), "v"(x));
+  else if constexpr (B == 1)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_1"
+        : "=v"(r) : "v"(e), "v"(x));
+  else if constexpr (B == 2)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_2"
+        : "=v"(r) : "v"(e), "v"(x));
+  else
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:BYTE_3"
+        : "=v"(r) : "v"(e), "v"(x));
+  return r;
+}
+
+// 16 symbols without resets: eight two-symbol lookups (STEP 2, table in LDS
+// at address 0) or sixteen one-symbol lookups.  Returns the state after the
+// word; `c` receives the number of pattern ends in the word (STEP 2, exact
+// two-symbol counts) or a nonzero flag when any accepting state was visited.
+// For STEP 2 the two-bit columns are spread into byte lanes once per word
+// (columns of even grams times 4 in xa, odd grams in xb), so each lookup
+// costs one address instruction.
 template <int SHIFT, int STEP>
 __device__ __forceinline__ uint32_t walk16(const Tab& tb, uint32_t s, uint32_t cols, uint32_t& c) {
   static_assert(STEP == 1 || SHIFT == 6, "two-symbol tables need 64-byte rows");
-  uint32_t acc = 0;
   if constexpr (STEP == 2) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      uint32_t e = t2_lookup(tb, s, (cols >> (4 * j)) & 15u);
-      s = e & 0xFFFFu;
-      acc += e;
-    }
-    c = acc >> 24;
+    const uint32_t xa = (cols << 2) & 0x3C3C3C3Cu;
+    const uint32_t xb = (cols >> 2) & 0x3C3C3C3Cu;
+    const uint32_t e0 = lds_at(row_plus_byte<0>(s, xa));
+    const uint32_t e1 = lds_at(row_plus_byte<0>(e0, xb));
+    const uint32_t e2 = lds_at(row_plus_byte<1>(e1, xa));
+    const uint32_t e3 = lds_at(row_plus_byte<1>(e2, xb));
+    const uint32_t e4 = lds_at(row_plus_byte<2>(e3, xa));
+    const uint32_t e5 = lds_at(row_plus_byte<2>(e4, xb));
+    const uint32_t e6 = lds_at(row_plus_byte<3>(e5, xa));
+    const uint32_t e7 = lds_at(row_plus_byte<3>(e6, xb));
+    c = (e0 + e1 + e2 + e3 + e4 + e5 + e6 + e7) >> 24;
+    return e7 & 0xFFFFu;
   } else {
+    uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       uint32_t e = t1_lookup<SHIFT>(tb, s, (cols >> (2 * j)) & 3u);
@@ -312,8 +347,8 @@ __device__ __forceinline__ uint32_t walk16(const Tab& tb, uint32_t s, uint32_t c
       acc |= e;
     }
     c = acc >> 16;
+    return s;
   }
-  return s;
 }
 
 // One 16-base word with reset bits `rst`.  Words without resets and words
