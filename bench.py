@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device three times (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -122,9 +124,18 @@ def main():
 
     import numpy as np
     import torch
-    import paper_1509_01506_amd as coex
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 1 << 30, "copy_bytes_written_per_launch": 1 << 30}))
+        return
+
+    import paper_1509_01506_amd as coex
     t0 = time.perf_counter()
     w = build_workload(args.workload)
     log("workload generated in %.1f s" % (time.perf_counter() - t0))
@@ -182,7 +193,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["desc"], "bases": w["n"], "automaton_states": info.n_states,
                    "patterns": info.n_patterns, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_spec_tail", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_tail", "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(k_avg_ms, 4),
                      "algorithmic_bytes_per_launch": int(algo_bytes)},
