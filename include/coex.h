@@ -97,6 +97,8 @@ typedef struct {
 
 #define COEX_FLAG_CHECK 1u
 #define COEX_FLAG_TIME 2u  /* record HIP events around the scan kernel (see coex_profile) */
+#define COEX_FLAG_GRAPH 4u /* batches: capture the launch sequence in a HIP graph at the first run
+                              and replay it on later runs */
 
 /* Facts about a compiled automaton. */
 typedef struct {
@@ -173,9 +175,71 @@ int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32
 int coex_count_chunks(const coex_dfa* dfa, const coex_seq* seq, uint32_t chunk, uint32_t* init_dev,
                       uint32_t* last_dev, uint64_t* counts_dev, void* stream);
 
-/* Counts for every (sequence, automaton) pair: counts_dev[s * n_dfa + d] =
-   total number of matches (all pattern ids) of dfas[d] in seqs[s].  All pairs
-   run in one persistent launch.  Asynchronous. */
+/* ------------------------------------------------------------ batches
+   Many sequences and automata in one persistent launch.  Per pair the method
+   is the one above (Section III, Algorithm 1): chunks, possible starting
+   states from a lookback table, lockstep speculative runs to the converging
+   point, one scan of the rest of each chunk, the join and the count fix-up.
+   Chunks of one sequence have `chunk` bases except the last, which also takes
+   the remainder (a sequence shorter than `chunk` is one chunk). */
+
+typedef struct coex_dfa_set coex_dfa_set;
+typedef struct coex_batch coex_batch;
+
+/* Resident automata: their tables packed into LDS groups on the current
+   device (two-symbol rows for automata of at most 1024 states and at most 15
+   patterns per state, one-symbol rows for the others; a group holds up to
+   1024 or 4096 states of one kind).  opts may be NULL; opts->width caps the possible starting
+   states a lane runs in lockstep (8 or 16, default 16) and opts->step forces
+   1 or 2 symbols per lookup.  The automata handles must outlive nothing: the
+   set copies what it needs.  Errors: EINVAL, ETOOBIG (an automaton above 4096
+   states), EUNSUPPORTED (an automaton whose possible starting states exceed
+   the width at every lookback k <= 8, or more than 255 patterns per state),
+   ENOMEM, EDEVICE. */
+int coex_dfa_set_create(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_opts* opts, coex_dfa_set** out);
+void coex_dfa_set_free(coex_dfa_set* set);
+
+/* A batch over `set`: pairs (pair_seq[i], pair_dfa[i]) of sequence and
+   automaton indices, i < n_pairs (host arrays, copied); both NULL = every
+   sequence with every automaton, pair index s * n_dfa + d.  Sequences are
+   device-resident (16-byte aligned) and must all use one encoding; the batch
+   keeps their pointers, so they must stay valid while it is run.
+   opts->chunk: bases per chunk (>= 64; 0 = chosen from the batch size and
+   the GPU); flags: COEX_FLAG_CHECK, COEX_FLAG_TIME (events around the scan
+   kernel, or the whole graph; read by coex_batch_info), COEX_FLAG_GRAPH.
+   Synchronous (uploads descriptors).  Errors: EINVAL, ENOMEM, EDEVICE. */
+int coex_batch_create(const coex_dfa_set* set, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
+                      const uint32_t* pair_dfa, uint32_t n_pairs, const coex_opts* opts, coex_batch** out);
+
+/* Runs the batch: counts_dev uint64[n_pairs] receives the total number of
+   matches (all pattern ids) of each pair.  Asynchronous on `stream` unless
+   COEX_FLAG_CHECK was given.  Runs of one batch must not overlap. */
+int coex_batch_run(coex_batch* batch, uint64_t* counts_dev, void* stream);
+
+/* Autotuner: runs the batch with chunk lengths 4 KiB, 16 KiB, ..., 1 MiB,
+   times each with HIP events (after one warm-up run each), keeps the fastest
+   and reports it in *chunk_out.  counts_dev as for coex_batch_run (holds the
+   last run's exact counts).  Synchronises `stream`. */
+int coex_batch_tune(coex_batch* batch, uint64_t* counts_dev, void* stream, uint64_t* chunk_out);
+
+typedef struct {
+  uint64_t chunk;     /* bases per chunk */
+  uint32_t width;     /* candidate registers per lane (8 or 16) */
+  uint32_t step;      /* symbols per LDS lookup: 1 or 2 (every group), 3 = groups of both kinds */
+  uint32_t n_groups;  /* LDS groups of the automaton set */
+  uint32_t n_pairs;
+  uint32_t n_tasks;   /* 768-lane tasks of the persistent launch */
+  uint32_t blocks;    /* persistent blocks */
+  uint64_t n_lanes;   /* (chunk, automaton) work items */
+  double last_ms;     /* device time of the last COEX_FLAG_TIME run, -1 if none (waits for it) */
+} coex_batch_info_t;
+
+int coex_batch_info(const coex_batch* batch, coex_batch_info_t* info);
+void coex_batch_free(coex_batch* batch);
+
+/* Convenience: counts_dev[s * n_dfa + d] = total number of matches of
+   dfas[d] in seqs[s] (set + batch + one run, then both freed).  Synchronises
+   `stream`. */
 int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_seq* seqs, uint32_t n_seq,
                        uint64_t* counts_dev, const coex_opts* opts, void* stream);
 

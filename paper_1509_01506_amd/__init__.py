@@ -21,13 +21,16 @@ ENC_BYTE = 0
 ENC_2BIT = 1
 FLAG_CHECK = 1
 FLAG_TIME = 2
+FLAG_GRAPH = 4
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -5: "ECAPACITY",
           -6: "EDEVICE", -7: "EUNSUPPORTED", -8: "ESYNTAX", -9: "EINTERNAL"}
 
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_find", "coex_count_chunks",
-            "coex_count_batched", "coex_profile", "coex_strerror", "coex_version"]
+            "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
+            "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free", "coex_profile",
+            "coex_strerror", "coex_version"]
 
 
 class CoexError(RuntimeError):
@@ -54,7 +57,14 @@ class _Info(ctypes.Structure):
                 ("max_pss", ctypes.c_uint32 * 9)]
 
 
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint64), ("width", ctypes.c_uint32), ("step", ctypes.c_uint32),
+                ("n_groups", ctypes.c_uint32), ("n_pairs", ctypes.c_uint32), ("n_tasks", ctypes.c_uint32),
+                ("blocks", ctypes.c_uint32), ("n_lanes", ctypes.c_uint64), ("last_ms", ctypes.c_double)]
+
+
 _L = None
+_VOID = ("coex_dfa_free", "coex_strerror", "coex_version", "coex_dfa_set_free", "coex_batch_free")
 
 
 def _lib():
@@ -76,12 +86,21 @@ def _lib():
         L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
         L.coex_count_chunks.argtypes = [p, p, u32, p, p, p, p]
         L.coex_count_batched.argtypes = [p, u32, p, u32, p, p, p]
+        L.coex_dfa_set_create.argtypes = [p, u32, p, p]
+        L.coex_dfa_set_free.argtypes = [p]
+        L.coex_dfa_set_free.restype = None
+        L.coex_batch_create.argtypes = [p, p, u32, p, p, u32, p, p]
+        L.coex_batch_run.argtypes = [p, p, p]
+        L.coex_batch_tune.argtypes = [p, p, p, p]
+        L.coex_batch_info.argtypes = [p, p]
+        L.coex_batch_free.argtypes = [p]
+        L.coex_batch_free.restype = None
         L.coex_profile.argtypes = [p, p, p, ci]
         L.coex_strerror.argtypes = [ci]
         L.coex_strerror.restype = ctypes.c_char_p
         L.coex_version.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("coex_dfa_free", "coex_strerror", "coex_version"):
+            if name not in _VOID:
                 getattr(L, name).restype = ci
         _L = L
     return _L
@@ -207,8 +226,9 @@ def to_device(data: np.ndarray, n: Optional[int] = None, encoding: int = ENC_BYT
     return DeviceSeq(b, int(n), encoding, m)
 
 
-def _opts(chunk=0, width=0, lookback=0, step=0, check=False, timed=False) -> _Opts:
-    return _Opts(chunk, width, lookback, step, (FLAG_CHECK if check else 0) | (FLAG_TIME if timed else 0))
+def _opts(chunk=0, width=0, lookback=0, step=0, check=False, timed=False, graph=False) -> _Opts:
+    return _Opts(chunk, width, lookback, step,
+                 (FLAG_CHECK if check else 0) | (FLAG_TIME if timed else 0) | (FLAG_GRAPH if graph else 0))
 
 
 def _stream(stream):
@@ -286,6 +306,111 @@ def count_batched(dfas: Sequence[Dfa], seqs: Sequence[DeviceSeq], out=None, chun
                                      len(seqs), out.data_ptr(), ctypes.byref(o), _stream(stream)),
            "count_batched")
     return out
+
+
+class DfaSet:
+    """Resident automata packed into LDS groups (coex_dfa_set)."""
+
+    def __init__(self, dfas: Sequence[Dfa], width: int = 0, step: int = 0):
+        self.dfas = list(dfas)
+        hs = (ctypes.c_void_p * len(self.dfas))(*[d.handle.value for d in self.dfas])
+        o = _opts(width=width, step=step)
+        out = ctypes.c_void_p()
+        _check(_lib().coex_dfa_set_create(ctypes.cast(hs, ctypes.c_void_p), len(self.dfas), ctypes.byref(o),
+                                          ctypes.byref(out)), "dfa_set_create")
+        self._h = out
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib().coex_dfa_set_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+@dataclass
+class BatchInfo:
+    chunk: int
+    width: int
+    step: int
+    n_groups: int
+    n_pairs: int
+    n_tasks: int
+    blocks: int
+    n_lanes: int
+    last_ms: float
+
+
+class Batch:
+    """(sequence, automaton) pairs over a DfaSet, run in one persistent launch
+    (coex_batch).  pairs=None: every sequence with every automaton, result
+    shaped [n_seq, n_dfa]; else a list of (seq index, dfa index), result [n]."""
+
+    def __init__(self, dset: DfaSet, seqs: Sequence[DeviceSeq], pairs=None, chunk: int = 0, check: bool = False,
+                 timed: bool = False, graph: bool = False):
+        self.dset = dset
+        self.seqs = list(seqs)          # keeps the device buffers alive
+        ss = (_Seq * max(1, len(self.seqs)))(*[s._c() for s in self.seqs])
+        o = _opts(chunk=chunk, check=check, timed=timed, graph=graph)
+        out = ctypes.c_void_p()
+        if pairs is None:
+            self.shape = (len(self.seqs), len(dset.dfas))
+            ps = pd = None
+            n = 0
+        else:
+            arr = np.asarray(pairs, dtype=np.uint32).reshape(-1, 2)
+            ps = np.ascontiguousarray(arr[:, 0])
+            pd = np.ascontiguousarray(arr[:, 1])
+            n = arr.shape[0]
+            self.shape = (n,)
+        _check(_lib().coex_batch_create(dset.handle, ctypes.cast(ss, ctypes.c_void_p), len(self.seqs),
+                                        None if ps is None else ps.ctypes.data,
+                                        None if pd is None else pd.ctypes.data, n, ctypes.byref(o),
+                                        ctypes.byref(out)), "batch_create")
+        self._h = out
+        self.n_pairs = int(np.prod(self.shape))
+
+    def _out(self, out):
+        import torch
+        if out is None:
+            out = torch.empty(max(1, self.n_pairs), dtype=torch.int64, device=self.seqs[0].bases.device)
+        return out
+
+    def run(self, out=None, stream=None):
+        out = self._out(out)
+        _check(_lib().coex_batch_run(self._h, out.data_ptr(), _stream(stream)), "batch_run")
+        return out[: self.n_pairs].view(self.shape)
+
+    def tune(self, out=None, stream=None) -> int:
+        out = self._out(out)
+        c = ctypes.c_uint64(0)
+        _check(_lib().coex_batch_tune(self._h, out.data_ptr(), _stream(stream), ctypes.byref(c)), "batch_tune")
+        return int(c.value)
+
+    def info(self) -> BatchInfo:
+        x = _BatchInfo()
+        _check(_lib().coex_batch_info(self._h, ctypes.byref(x)), "batch_info")
+        return BatchInfo(int(x.chunk), x.width, x.step, x.n_groups, x.n_pairs, x.n_tasks, x.blocks,
+                         int(x.n_lanes), x.last_ms)
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib().coex_batch_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def profile(stream=None, reset: bool = True):

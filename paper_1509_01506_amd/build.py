@@ -44,19 +44,34 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     tag = ".tmp%d_%d" % (os.getpid(), abs(hash((out, tuple(defines)))) % 100000)
     sfx = tag.replace(".", "_")
     obj_host = os.path.join(CSRC, "compile%s.o" % sfx)
-    obj_dev = os.path.join(CSRC, "coex%s.o" % sfx)
+    dev_srcs = ["coex.hip", "batch.hip"]
+    obj_dev = [os.path.join(CSRC, "%s%s.o" % (os.path.splitext(f)[0], sfx)) for f in dev_srcs]
     tmp = out + tag
     try:
-        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", "-o", obj_host] + inc +
-             [os.path.join(CSRC, "compile.cpp")], verbose)
-        _run([hipcc()] + FLAGS + ["-D" + d for d in defines] + inc +
-             ["-c", "-o", obj_dev, os.path.join(CSRC, "coex.hip")], verbose)
+        jobs = [subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", "-o", obj_host] + inc +
+                                 [os.path.join(CSRC, "compile.cpp")],
+                                 stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)]
+        for src, obj in zip(dev_srcs, obj_dev):
+            cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + inc + ["-c", "-o", obj, os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            jobs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+        errs = []
+        for j in jobs:
+            _, err = j.communicate()
+            err = "\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l)
+            if j.returncode != 0:
+                errs.append(err)
+            elif verbose and err.strip():
+                print(err, file=sys.stderr)
+        if errs:
+            raise RuntimeError("compile failed:\n" + "\n".join(errs))
         rocm_lib = "/opt/rocm/lib"
-        _run(["g++", "-shared", "-o", tmp, obj_dev, obj_host, "-L" + rocm_lib, "-lamdhip64",
+        _run(["g++", "-shared", "-o", tmp] + obj_dev + [obj_host, "-L" + rocm_lib, "-lamdhip64",
               "-Wl,-rpath," + rocm_lib], verbose)
         os.replace(tmp, out)
     finally:
-        for f in (obj_host, obj_dev, tmp):
+        for f in [obj_host, tmp] + obj_dev:
             if os.path.exists(f):
                 os.remove(f)
     return out

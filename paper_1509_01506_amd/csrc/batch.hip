@@ -1,0 +1,1042 @@
+// libcoex batched scans: many (sequence, automaton) pairs in one persistent
+// launch, for a batch of uneven sequences crossed with a set of resident
+// automata (or any list of pairs, as a serving loop forms them).
+//
+// The method per pair is the paper's (Section III, Algorithm 1): the sequence
+// is cut into chunks; a chunk's possible starting states come from the k
+// bases before it (Section III.A with a k-base lookback); the candidate runs
+// advance in lockstep until they agree (the converging point,
+// Section III.B.3); the rest of the chunk is scanned once from there; the
+// join takes each chunk's true first state from its predecessor's last
+// state; the counts before the converging point are fixed up when the
+// candidates disagree on them.
+//
+// Layout on the GPU (one launch of k_bscan does all pairs):
+//   - automata are packed into LDS groups: the rows of every automaton of a
+//     group sit in one LDS image whose entries are absolute row offsets, so a
+//     lane's state register addresses its own automaton's rows directly;
+//     two-symbol rows (64 B) when every automaton's counts fit them, else
+//     one-symbol rows (16 B);
+//   - a lane owns one (chunk, automaton) pair; the pairs of one chunk are
+//     adjacent lanes, so a chunk is read from HBM once for all automata of
+//     its group (the lanes load the same lines);
+//   - blocks are persistent and take 768-lane tasks from a device counter;
+//     a block restages LDS only when its task moves to another group.
+// k_bcompose resolves chunks whose candidates never agreed (only automata
+// without a finite synchronising depth, or one longer than the chunk), and
+// k_bfix recounts the prefixes whose candidate counts differed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "coex.h"
+#include "dfa.hpp"
+#include "kernels.hpp"
+
+namespace coex {
+namespace batch {
+
+constexpr int kBlock = COEX_SCAN_BLOCK;
+constexpr uint32_t kPad = 0xFFFFFFFFu;      // pair slot without an automaton
+constexpr uint32_t kGroupStates2 = 1024;    // two-symbol rows: 16-bit row offsets of 64 B rows
+constexpr uint32_t kGroupStates1 = 4096;    // one-symbol rows: 16-bit row offsets of 16 B rows
+
+struct SeqD {
+  const uint8_t* bases;
+  const uint8_t* nmask;
+  uint64_t n;
+};
+struct DfaD {
+  uint32_t base;      // state register value of state 0 (its row offset in the group image)
+  uint32_t q0s;       // state register value of q0
+  uint32_t k;         // lookback of the possible-starting-state table
+  uint32_t group;
+  const uint32_t* pss_off;
+  const uint16_t* pss_states;
+};
+struct EntryD {       // one sequence with the automata of one group paired to it
+  uint32_t seq;
+  uint32_t slot0;     // first of the group's D pair slots
+  uint32_t n_chunks;
+  uint32_t unit0;     // first unit (global index)
+};
+struct UnitD {
+  uint32_t entry;
+  uint32_t chunk;
+};
+struct GroupD {
+  uint64_t lane0;     // first lane of the launch
+  uint64_t n_lanes;   // units * D
+  uint64_t unit0;     // first unit
+  uint32_t task0;     // first block task
+  uint32_t D;         // pair slots per entry
+  uint32_t tab_bytes; // LDS image bytes
+  uint32_t step;      // symbols per LDS lookup (2: 64 B rows, state = row offset; 1: 16 B rows)
+  const uint32_t* tab;   // LDS image
+  const uint32_t* t1;    // one-symbol rows in global memory, same register values
+  const uint32_t* wtab;  // weight (patterns) per accepting index of the group
+};
+struct Args {
+  const SeqD* seqs;
+  const DfaD* dfas;
+  const EntryD* entries;
+  const UnitD* units;
+  const GroupD* groups;
+  const uint32_t* slot_dfa;
+  const uint32_t* slot_out;
+  const uint32_t* slot_entry;
+  uint32_t n_groups, n_tasks, n_slots, bcast_off;
+  uint64_t chunk;
+  unsigned long long* counts;
+  uint32_t n_counts;
+  uint32_t* task_ctr;
+  uint32_t* fix_count;
+  uint32_t* fix_list;
+  uint32_t* err;
+  uint32_t* rec_t;     // symbols to the converging point, NONCONV if the candidates never agreed
+  uint32_t* rec_s;     // converged state
+  uint32_t* rec_end;   // state at the chunk end
+  uint32_t* rec_tail;  // matches after the converging point
+  uint32_t* rec_ts;    // true first state (written by k_bcompose)
+  uint32_t* nc_m;      // non-converged chunks: candidates, their end states and counts (lane * W)
+  uint32_t* nc_init;
+  uint32_t* nc_end;
+  uint32_t* nc_cnt;
+};
+
+__device__ __forceinline__ void stage(char* dst, const void* src, uint32_t bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__global__ void k_binit(Args A) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    *A.task_ctr = 0;
+    *A.fix_count = 0;
+    *A.err = 0;
+  }
+  for (uint32_t i = t; i < A.n_counts; i += gridDim.x * blockDim.x) A.counts[i] = 0;
+}
+
+// One (chunk, automaton) pair: candidates, lockstep speculation, the scan
+// after the converging point, and the chunk's records.
+template <int ENC, int SHIFT, int STEP, int W>
+__device__ __forceinline__ void lane_scan(const Args& A, const GroupD& G, const char* lds, uint64_t gl, uint64_t L) {
+  const uint32_t D = G.D;
+  const UnitD un = A.units[G.unit0 + L / D];
+  const uint32_t j = (uint32_t)(L % D);
+  const EntryD en = A.entries[un.entry];
+  const uint32_t slot = en.slot0 + j;
+  const uint32_t d = A.slot_dfa[slot];
+  if (d == kPad) return;
+  const DfaD df = A.dfas[d];
+  const SeqD sq = A.seqs[en.seq];
+  ScanArgs sa{};
+  sa.bases = sq.bases;
+  sa.nmask = sq.nmask;
+  sa.n = sq.n;
+  sa.k = df.k;
+  const uint64_t lo = (uint64_t)un.chunk * A.chunk;
+  const uint64_t hi = (un.chunk + 1 == en.n_chunks) ? sq.n : lo + A.chunk;
+  const Tab tg{nullptr, reinterpret_cast<const char*>(G.t1), df.q0s};
+  uint32_t m, cbase, exact;
+  bool is_exact;
+  chunk_header<ENC, SHIFT>(sa, tg, df.pss_off, lo, m, cbase, exact, is_exact);
+  if (m == 0 || m > (uint32_t)W) {
+    atomicOr(A.err, 1u);
+    return;
+  }
+  uint32_t cand[W], pc[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    cand[i] = 0;
+    pc[i] = 0;
+    if (i < (int)m) cand[i] = is_exact ? exact : df.base + ((uint32_t)df.pss_states[cbase + i] << SHIFT);
+  }
+  // lockstep runs of the candidates until they agree
+  uint64_t p = lo;
+  bool conv = m == 1;
+  while (!conv && p < hi) {
+    const int col = load_col<ENC>(sa, p);
+    bool same = true;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if (i < (int)m) {
+        uint32_t s2 = df.q0s;
+        if (col >= 0) {
+          const uint32_t e = t1_lookup<SHIFT>(tg, cand[i], (uint32_t)col);
+          s2 = e & 0xFFFFu;
+          if (e >> 16) pc[i] += G.wtab[(e >> 16) - 1u];
+        }
+        cand[i] = s2;
+        same = same && s2 == cand[0];
+      }
+    }
+    ++p;
+    conv = same;
+  }
+  if (!conv && !A.nc_m) {  // cannot happen when the chunk exceeds every synchronising depth
+    atomicOr(A.err, 8u);
+    A.rec_t[gl] = 0;
+    A.rec_end[gl] = cand[0];
+    return;
+  }
+  if (!conv) {  // the chunk's state map on its candidates
+    A.rec_t[gl] = NONCONV;
+    A.nc_m[gl] = m;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if (i < (int)m) {
+        const uint64_t x = gl * W + i;
+        A.nc_init[x] = df.base + ((uint32_t)df.pss_states[cbase + i] << SHIFT);
+        A.nc_end[x] = cand[i];
+        A.nc_cnt[x] = pc[i];
+      }
+    }
+    return;
+  }
+  bool common = true;
+#pragma unroll
+  for (int i = 1; i < W; ++i)
+    if (i < (int)m) common = common && pc[i] == pc[0];
+  const uint32_t s0 = cand[0];
+  const uint32_t prefix = pc[0];
+  const Tab tb{lds, STEP == 2 ? reinterpret_cast<const char*>(G.t1) : lds, df.q0s};
+  SinkTotal sink{G.wtab};
+  const uint32_t e_end = scan_range<ENC, SHIFT, STEP>(sa, tb, s0, p, hi, sink);
+  A.rec_end[gl] = e_end;
+  A.rec_t[gl] = (uint32_t)(p - lo);
+  if (common) {
+    const uint64_t tot = (uint64_t)prefix + sink.cnt;
+    if (tot) atomicAdd(A.counts + A.slot_out[slot], (unsigned long long)tot);
+  } else {
+    A.rec_s[gl] = s0;
+    A.rec_tail[gl] = sink.cnt;
+    A.fix_list[atomicAdd(A.fix_count, 1u)] = (uint32_t)gl;
+  }
+}
+
+// Persistent scan: every block takes 768-lane tasks until the counter passes
+// the last one (every wave reaches the exit).  LDS holds the group image at
+// address 0 and one broadcast word after it.
+template <int ENC, int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W == 8 ? COEX_TAIL_WAVES : 4, 8))) void k_bscan(Args A) {
+  extern __shared__ __align__(16) char lds[];
+  uint32_t* bc = reinterpret_cast<uint32_t*>(lds + A.bcast_off);
+  if (threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(A.err, 64u);
+  int staged = -1;
+  for (;;) {
+    if (threadIdx.x == 0) bc[0] = atomicAdd(A.task_ctr, 1u);
+    __syncthreads();
+    const uint32_t task = bc[0];
+    if (task >= A.n_tasks) break;
+    uint32_t g = 0;
+    while (g + 1 < A.n_groups && A.groups[g + 1].task0 <= task) ++g;
+    GroupD G = A.groups[g];
+    // group fields are uniform over the block: keep them in scalar registers
+    G.D = __builtin_amdgcn_readfirstlane(G.D);
+    G.step = __builtin_amdgcn_readfirstlane(G.step);
+    G.unit0 = uniform64(G.unit0);
+    G.lane0 = uniform64(G.lane0);
+    G.n_lanes = uniform64(G.n_lanes);
+    G.t1 = reinterpret_cast<const uint32_t*>(uniform64(reinterpret_cast<uint64_t>(G.t1)));
+    G.wtab = reinterpret_cast<const uint32_t*>(uniform64(reinterpret_cast<uint64_t>(G.wtab)));
+    if ((int)g != staged) {
+      stage(lds, G.tab, G.tab_bytes);
+      staged = (int)g;
+    }
+    __syncthreads();
+    const uint64_t L = (uint64_t)(task - G.task0) * kBlock + threadIdx.x;
+    if (L < G.n_lanes) {
+      if (G.step == 2) lane_scan<ENC, 6, 2, W>(A, G, lds, G.lane0 + L, L);
+      else lane_scan<ENC, 4, 1, W>(A, G, lds, G.lane0 + L, L);
+    }
+    __syncthreads();
+  }
+}
+
+// The join for pairs with non-converged chunks: one thread per pair slot
+// walks its chunks in order, picking each non-converged chunk's map entry
+// for the true first state and recording the true first state of the
+// others for the fix-up.
+template <int W>
+__global__ void k_bcompose(Args A) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= A.n_slots) return;
+  const uint32_t d = A.slot_dfa[x];
+  if (d == kPad) return;
+  const DfaD df = A.dfas[d];
+  const EntryD en = A.entries[A.slot_entry[x]];
+  const GroupD G = A.groups[df.group];
+  const uint32_t j = x - en.slot0;
+  uint32_t q = df.q0s;
+  unsigned long long add = 0;
+  for (uint32_t c = 0; c < en.n_chunks; ++c) {
+    const uint64_t gl = G.lane0 + (uint64_t)(en.unit0 - G.unit0 + c) * G.D + j;
+    if (A.rec_t[gl] == NONCONV) {
+      const uint32_t m = A.nc_m[gl];
+      uint32_t i = 0;
+      while (i < m && A.nc_init[gl * W + i] != q) ++i;
+      if (i == m) {
+        atomicOr(A.err, 4u);
+        return;
+      }
+      add += A.nc_cnt[gl * W + i];
+      q = A.nc_end[gl * W + i];
+    } else {
+      A.rec_ts[gl] = q;
+      q = A.rec_end[gl];
+    }
+  }
+  if (add) atomicAdd(A.counts + A.slot_out[x], add);
+}
+
+// Prefix recount of the chunks whose candidates disagreed on the count
+// before the converging point: from the true first state (the predecessor's
+// last state) to the converging point, which it must reach.
+template <int ENC>
+__global__ void k_bfix(Args A) {
+  const uint32_t nf = *A.fix_count;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x) {
+    const uint32_t gl = A.fix_list[i];
+    uint32_t g = 0;
+    while (g + 1 < A.n_groups && A.groups[g + 1].lane0 <= gl) ++g;
+    const GroupD G = A.groups[g];
+    const uint64_t L = gl - G.lane0;
+    const UnitD un = A.units[G.unit0 + L / G.D];
+    const EntryD en = A.entries[un.entry];
+    const uint32_t slot = en.slot0 + (uint32_t)(L % G.D);
+    const DfaD df = A.dfas[A.slot_dfa[slot]];
+    const SeqD sq = A.seqs[en.seq];
+    ScanArgs sa{};
+    sa.bases = sq.bases;
+    sa.nmask = sq.nmask;
+    sa.n = sq.n;
+    const char* t1 = reinterpret_cast<const char*>(G.t1);
+    const uint32_t sh = G.step == 2 ? 2u : 0u;  // state register -> one-symbol row offset
+    const uint32_t prev = gl - G.D;
+    uint32_t q = A.rec_t[prev] == NONCONV ? A.rec_ts[gl] : A.rec_end[prev];
+    const uint64_t lo = (uint64_t)un.chunk * A.chunk;
+    const uint32_t t = A.rec_t[gl];
+    uint32_t cnt = 0;
+    for (uint32_t s = 0; s < t; ++s) {
+      const int col = load_col<ENC>(sa, lo + s);
+      if (col < 0) {
+        q = df.q0s;
+        continue;
+      }
+      const uint32_t e = *reinterpret_cast<const uint32_t*>(t1 + (q >> sh) + (uint32_t)col * 4u);
+      q = e & 0xFFFFu;
+      if (e >> 16) cnt += G.wtab[(e >> 16) - 1u];
+    }
+    if (q != A.rec_s[gl]) atomicOr(A.err, 2u);
+    const uint64_t tot = (uint64_t)cnt + A.rec_tail[gl];
+    if (tot) atomicAdd(A.counts + A.slot_out[slot], (unsigned long long)tot);
+  }
+}
+
+// ====================================================================== host
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+const int kOrd2bit[4] = {0, 1, 2, 3};  // column j holds the successor on code ord[j]
+const int kOrdByte[4] = {0, 1, 3, 2};
+
+struct DevBuf {
+  char* p = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) {
+      int cur = -1;
+      if (hipGetDevice(&cur) == hipSuccess && cur != device) (void)hipSetDevice(device);
+      (void)hipFree(p);
+      if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+    }
+    p = nullptr;
+    bytes = 0;
+  }
+  int reserve(size_t want, int dev) {
+    if (bytes >= want && device == dev) return COEX_OK;
+    release();
+    want = std::max<size_t>(want, 4096);
+    if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return COEX_ENOMEM; }
+    bytes = want;
+    device = dev;
+    return COEX_OK;
+  }
+};
+
+// Host image assembled part by part, then copied to one device buffer.
+struct Image {
+  std::vector<char> host;
+  size_t add(const void* src, size_t bytes) {
+    const size_t off = host.size();
+    host.resize(align_up(off + std::max<size_t>(bytes, 16), 256), 0);
+    if (bytes) std::memcpy(host.data() + off, src, bytes);
+    return off;
+  }
+};
+
+int device_cus(int dev, int& n_cu) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) { n_cu = it->second; return COEX_OK; }
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return COEX_EDEVICE;
+  cache[dev] = v;
+  n_cu = v;
+  return COEX_OK;
+}
+
+}  // namespace batch
+}  // namespace coex
+
+// Resident automata, grouped for LDS (the handle behind coex_dfa_set).
+struct coex_dfa_set {
+  int device = 0;
+  uint32_t n_dfa = 0;
+  uint32_t W = 8;
+  bool any_step2 = false, any_step1 = false;
+  bool may_not_converge_below = false;  // some automaton has no finite synchronising depth
+  uint32_t max_sync = 0;                // largest finite synchronising depth (+ lookback)
+  std::vector<uint32_t> n_states, group_of, k_of;
+  struct Group {
+    std::vector<uint32_t> members;
+    uint32_t step = 2;
+    uint32_t n_states = 0, n_acc = 0, tab_bytes = 0;
+    size_t off_tab[2], off_t1[2], off_w;
+  };
+  std::vector<Group> groups;
+  // per automaton device descriptors per encoding (byte, 2-bit)
+  std::vector<coex::batch::DfaD> dfa_dev[2];
+  std::vector<coex::batch::GroupD> group_dev[2];  // lane fields filled per batch
+  coex::batch::DevBuf buf;
+};
+
+// A batch of pairs over one automaton set (the handle behind coex_batch).
+struct coex_batch {
+  const coex_dfa_set* set = nullptr;
+  int device = 0, n_cu = 0, enc = 0;
+  uint64_t chunk = 0;
+  uint32_t n_pairs = 0, flags = 0, blocks = 0, lds_bytes = 0;
+  bool needs_nc = false;
+  // host descriptors (kept to rebuild with another chunk length)
+  std::vector<coex::batch::SeqD> seqs;
+  std::vector<uint32_t> pair_seq, pair_dfa;
+  uint64_t n_lanes = 0, n_units = 0;
+  uint32_t n_tasks = 0, n_slots = 0, max_D = 0;
+  coex::batch::Args args{};
+  coex::batch::DevBuf desc, recs;
+  // graph replay
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  unsigned long long* graph_counts = nullptr;
+  // timing of the last timed run
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed_pending = false;
+  ~coex_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace coex {
+namespace batch {
+
+using Set = coex_dfa_set;
+using Batch = coex_batch;
+
+int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std::unique_ptr<Set>& out) {
+  if (!hs || n_dfa == 0) return COEX_EINVAL;
+  auto S = std::make_unique<Set>();
+  if (hipGetDevice(&S->device) != hipSuccess) return COEX_EDEVICE;
+  S->n_dfa = n_dfa;
+  std::vector<const Dfa*> ds(n_dfa);
+  std::vector<uint32_t> step_of(n_dfa, 2);
+  uint32_t wmax = (o && o->width) ? o->width : 16u;
+  if (wmax != 1 && wmax != 8 && wmax != 16) {
+    if (wmax > 16) return COEX_EUNSUPPORTED;
+    wmax = wmax <= 8 ? 8u : 16u;
+  }
+  for (uint32_t i = 0; i < n_dfa; ++i) {
+    if (!hs[i]) return COEX_EINVAL;
+    ds[i] = reinterpret_cast<const Dfa*>(hs[i]);
+    // two-symbol rows need 64 B rows addressable with 16 bits and exact
+    // 8-bit counts over a 16-base word
+    const bool t2_ok = ds[i]->max_out <= 15 && ds[i]->n_states <= kGroupStates2;
+    if (ds[i]->n_states > kGroupStates1) return COEX_ETOOBIG;
+    if (ds[i]->max_out > 255) return COEX_EUNSUPPORTED;
+    if (o && o->step == 2 && !t2_ok) return COEX_EUNSUPPORTED;
+    step_of[i] = (o && o->step == 1) ? 1u : (t2_ok ? 2u : 1u);
+    (step_of[i] == 2 ? S->any_step2 : S->any_step1) = true;
+  }
+  // lookback per automaton: the shortest whose largest candidate list fits
+  // the width (8 if possible, else the width asked for)
+  S->k_of.resize(n_dfa);
+  uint32_t W = 1;
+  for (uint32_t i = 0; i < n_dfa; ++i) {
+    const Dfa& d = *ds[i];
+    uint32_t k = 0;
+    for (uint32_t kk = 1; kk <= kMaxLookback && !k; ++kk)
+      if (d.pss[kk].max_size <= std::min<uint32_t>(8, wmax)) k = kk;
+    for (uint32_t kk = 1; kk <= kMaxLookback && !k; ++kk)
+      if (d.pss[kk].max_size <= wmax) k = kk;
+    if (!k) return COEX_EUNSUPPORTED;
+    S->k_of[i] = k;
+    W = std::max(W, d.pss[k].max_size);
+    if (d.sync_depth == kNoSync) S->may_not_converge_below = true;
+    else S->max_sync = std::max(S->max_sync, d.sync_depth + k);
+  }
+  S->W = W <= 8 ? 8u : 16u;
+  // groups: first fit by decreasing size among automata of the same step
+  std::vector<uint32_t> order(n_dfa);
+  for (uint32_t i = 0; i < n_dfa; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return ds[a]->n_states > ds[b]->n_states; });
+  S->group_of.assign(n_dfa, 0);
+  S->n_states.resize(n_dfa);
+  for (uint32_t i : order) {
+    const uint32_t n = ds[i]->n_states;
+    const uint32_t cap = step_of[i] == 2 ? kGroupStates2 : kGroupStates1;
+    S->n_states[i] = n;
+    uint32_t g = 0;
+    while (g < S->groups.size() && (S->groups[g].step != step_of[i] || S->groups[g].n_states + n > cap)) ++g;
+    if (g == S->groups.size()) {
+      S->groups.emplace_back();
+      S->groups.back().step = step_of[i];
+    }
+    S->groups[g].members.push_back(i);
+    S->groups[g].n_states += n;
+    S->group_of[i] = g;
+  }
+  // images
+  Image img;
+  std::vector<uint32_t> base(n_dfa), acc_base(n_dfa), shift_of(n_dfa);
+  for (auto& G : S->groups) {
+    const uint32_t SH = G.step == 2 ? 6u : 4u;
+    const uint32_t row = G.step == 2 ? 64u : 16u;
+    for (uint32_t i : G.members) shift_of[i] = SH;
+    uint32_t st = 0, ac = 0;
+    for (uint32_t i : G.members) {
+      base[i] = st * row;
+      acc_base[i] = ac;
+      st += ds[i]->n_states;
+      ac += ds[i]->n_accepting;
+    }
+    G.n_acc = ac;
+    G.tab_bytes = (uint32_t)align_up((size_t)st * row, 16);
+    std::vector<uint32_t> w(std::max<uint32_t>(ac, 1), 0);
+    for (uint32_t i : G.members) {
+      const Dfa& d = *ds[i];
+      for (uint32_t a = 0; a < d.n_accepting; ++a) {
+        const uint32_t s = d.acc_state[a];
+        w[acc_base[i] + a] = d.out_off[s + 1] - d.out_off[s];
+      }
+    }
+    G.off_w = img.add(w.data(), w.size() * 4);
+    for (int e = 0; e < 2; ++e) {
+      const int* ord = e == 1 ? kOrd2bit : kOrdByte;
+      std::vector<uint32_t> t1((size_t)st * 4), t2;
+      if (G.step == 2) t2.resize((size_t)st * 16);
+      for (uint32_t i : G.members) {
+        const Dfa& d = *ds[i];
+        auto reg = [&](uint32_t s) { return base[i] + (s << SH); };
+        auto wt = [&](uint32_t s) { return d.out_off[s + 1] - d.out_off[s]; };
+        const uint32_t r0 = base[i] / row;
+        for (uint32_t s = 0; s < d.n_states; ++s) {
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t t = d.delta[s * 4 + ord[c]];
+            const uint32_t a = d.acc_index[t] >= 0 ? acc_base[i] + (uint32_t)d.acc_index[t] + 1u : 0u;
+            t1[(size_t)(r0 + s) * 4 + c] = reg(t) | (a << 16);
+          }
+          if (G.step == 2)
+            for (int g = 0; g < 16; ++g) {
+              const uint32_t s1 = d.delta[s * 4 + ord[g & 3]];
+              const uint32_t s2 = d.delta[s1 * 4 + ord[g >> 2]];
+              t2[(size_t)(r0 + s) * 16 + g] = reg(s2) | ((wt(s1) + wt(s2)) << 24);
+            }
+        }
+      }
+      G.off_t1[e] = img.add(t1.data(), t1.size() * 4);
+      G.off_tab[e] = G.step == 2 ? img.add(t2.data(), t2.size() * 4) : G.off_t1[e];
+    }
+  }
+  std::vector<size_t> off_po(n_dfa), off_ps(n_dfa);
+  for (uint32_t i = 0; i < n_dfa; ++i) {
+    const PssTable& P = ds[i]->pss[S->k_of[i]];
+    off_po[i] = img.add(P.off.data(), P.off.size() * 4);
+    off_ps[i] = img.add(P.states.data(), P.states.size() * 2);
+  }
+  int rc = S->buf.reserve(img.host.size(), S->device);
+  if (rc) return rc;
+  if (hipMemcpy(S->buf.p, img.host.data(), img.host.size(), hipMemcpyHostToDevice) != hipSuccess) return COEX_EDEVICE;
+  for (int e = 0; e < 2; ++e) {
+    S->dfa_dev[e].resize(n_dfa);
+    for (uint32_t i = 0; i < n_dfa; ++i) {
+      DfaD& D = S->dfa_dev[e][i];
+      D.base = base[i];
+      D.q0s = base[i] + (ds[i]->q0 << shift_of[i]);
+      D.k = S->k_of[i];
+      D.group = S->group_of[i];
+      D.pss_off = reinterpret_cast<const uint32_t*>(S->buf.p + off_po[i]);
+      D.pss_states = reinterpret_cast<const uint16_t*>(S->buf.p + off_ps[i]);
+    }
+    S->group_dev[e].resize(S->groups.size());
+    for (size_t g = 0; g < S->groups.size(); ++g) {
+      GroupD& G = S->group_dev[e][g];
+      G = GroupD{};
+      G.tab_bytes = S->groups[g].tab_bytes;
+      G.step = S->groups[g].step;
+      G.tab = reinterpret_cast<const uint32_t*>(S->buf.p + S->groups[g].off_tab[e]);
+      G.t1 = reinterpret_cast<const uint32_t*>(S->buf.p + S->groups[g].off_t1[e]);
+      G.wtab = reinterpret_cast<const uint32_t*>(S->buf.p + S->groups[g].off_w);
+    }
+  }
+  out = std::move(S);
+  return COEX_OK;
+}
+
+template <int ENC, int W>
+int occupancy(uint32_t lds) {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bscan<ENC, W>, kBlock, lds) != hipSuccess) return 1;
+  return std::max(1, b);
+}
+
+template <int ENC, int W>
+void launch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs_only) {
+  Args& A = B.args;
+  if (attrs_only) {
+    (void)hipFuncSetAttribute((const void*)k_bscan<ENC, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)B.lds_bytes);
+    return;
+  }
+  hipLaunchKernelGGL(k_binit, dim3(std::max<uint32_t>(1, std::min<uint32_t>((B.n_pairs + 255) / 256, 1024))),
+                     dim3(256), 0, st, A);
+  if (B.n_tasks) {
+    if (e0) (void)hipEventRecord(e0, st);
+    hipLaunchKernelGGL((k_bscan<ENC, W>), dim3(B.blocks), dim3(kBlock), B.lds_bytes, st, A);
+    if (e1) (void)hipEventRecord(e1, st);
+    if (B.needs_nc)
+      hipLaunchKernelGGL(k_bcompose<W>, dim3((B.n_slots + 255) / 256), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_bfix<ENC>, dim3(std::max(1, B.n_cu)), dim3(256), 0, st, A);
+  }
+}
+
+// attrs_only: set the scan kernel's LDS limit (outside any graph capture).
+void dispatch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs_only = false) {
+  const Set& S = *B.set;
+  const bool by = B.enc == 0;
+  const bool a = attrs_only;
+  if (S.W == 8) by ? launch<ENC_BYTE, 8>(B, st, e0, e1, a) : launch<ENC_2BIT, 8>(B, st, e0, e1, a);
+  else by ? launch<ENC_BYTE, 16>(B, st, e0, e1, a) : launch<ENC_2BIT, 16>(B, st, e0, e1, a);
+}
+
+uint32_t blocks_per_cu(const Set& S, int enc, uint32_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, uint32_t, uint32_t>, int> cache;
+  const auto key = std::make_tuple(enc, S.W, lds);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return (uint32_t)it->second;
+  const bool by = enc == 0;
+  const int b = S.W == 8 ? (by ? occupancy<ENC_BYTE, 8>(lds) : occupancy<ENC_2BIT, 8>(lds))
+                         : (by ? occupancy<ENC_BYTE, 16>(lds) : occupancy<ENC_2BIT, 16>(lds));
+  cache[key] = b;
+  return (uint32_t)b;
+}
+
+// Chunk length when none is given: about three tasks' worth of lanes per
+// resident lane of the GPU, between 4 KiB and 1 MiB, a multiple of 4 KiB.
+uint64_t default_chunk(const Batch& B, uint64_t lane_bases) {
+  const uint64_t resident = (uint64_t)std::max(1, B.n_cu) * 2 * kBlock;
+  uint64_t c = lane_bases / std::max<uint64_t>(1, 3 * resident);
+  c = std::max<uint64_t>(4096, std::min<uint64_t>(c, 1ull << 20));
+  return align_up(c, 4096);
+}
+
+// Descriptors and records for the current chunk length.
+int layout(Batch& B) {
+  const Set& S = *B.set;
+  const int e = B.enc;
+  const uint64_t C = B.chunk;
+  const size_t ng = S.groups.size();
+  // entries: (group, sequence) with the pair slots of that group
+  std::vector<std::vector<std::vector<uint32_t>>> by_group(ng, std::vector<std::vector<uint32_t>>(B.seqs.size()));
+  for (uint32_t i = 0; i < B.n_pairs; ++i) by_group[S.group_of[B.pair_dfa[i]]][B.pair_seq[i]].push_back(i);
+  std::vector<EntryD> entries;
+  std::vector<UnitD> units;
+  std::vector<uint32_t> slot_dfa, slot_out, slot_entry;
+  std::vector<GroupD> groups = S.group_dev[e];
+  uint64_t lane0 = 0;
+  uint32_t task0 = 0;
+  B.max_D = 0;
+  for (size_t g = 0; g < ng; ++g) {
+    uint32_t D = 0;
+    for (auto& v : by_group[g]) D = std::max<uint32_t>(D, (uint32_t)v.size());
+    GroupD& G = groups[g];
+    G.D = std::max<uint32_t>(D, 1);
+    G.unit0 = units.size();
+    G.lane0 = lane0;
+    G.task0 = task0;
+    for (uint32_t s = 0; s < B.seqs.size(); ++s) {
+      auto& v = by_group[g][s];
+      if (v.empty()) continue;
+      const uint64_t n = B.seqs[s].n;
+      const uint64_t K = n == 0 ? 0 : std::max<uint64_t>(1, n / C);
+      if (K > 0xFFFFFFFFull) return COEX_EINVAL;
+      EntryD en{};
+      en.seq = s;
+      en.slot0 = (uint32_t)slot_dfa.size();
+      en.n_chunks = (uint32_t)K;
+      en.unit0 = (uint32_t)units.size();
+      const uint32_t eid = (uint32_t)entries.size();
+      for (uint32_t jj = 0; jj < G.D; ++jj) {
+        slot_dfa.push_back(jj < v.size() ? B.pair_dfa[v[jj]] : kPad);
+        slot_out.push_back(jj < v.size() ? v[jj] : 0u);
+        slot_entry.push_back(eid);
+      }
+      for (uint64_t c = 0; c < K; ++c) units.push_back(UnitD{eid, (uint32_t)c});
+      entries.push_back(en);
+    }
+    G.n_lanes = (units.size() - G.unit0) * (uint64_t)G.D;
+    lane0 += G.n_lanes;
+    task0 += (uint32_t)((G.n_lanes + kBlock - 1) / kBlock);
+    B.max_D = std::max(B.max_D, G.D);
+  }
+  if (units.size() > 0xFFFFFFFFull || lane0 > 0xFFFFFFFFull) return COEX_EINVAL;
+  B.n_lanes = lane0;
+  B.n_units = units.size();
+  B.n_tasks = task0;
+  B.n_slots = (uint32_t)slot_dfa.size();
+  // chunks may fail to converge only when an automaton's synchronising depth
+  // (plus its lookback) reaches the chunk length
+  B.needs_nc = S.may_not_converge_below || S.max_sync >= C;
+  Image img;
+  const size_t o_seq = img.add(B.seqs.data(), B.seqs.size() * sizeof(SeqD));
+  const size_t o_dfa = img.add(S.dfa_dev[e].data(), S.dfa_dev[e].size() * sizeof(DfaD));
+  const size_t o_ent = img.add(entries.data(), entries.size() * sizeof(EntryD));
+  const size_t o_unit = img.add(units.data(), units.size() * sizeof(UnitD));
+  const size_t o_grp = img.add(groups.data(), groups.size() * sizeof(GroupD));
+  const size_t o_sd = img.add(slot_dfa.data(), slot_dfa.size() * 4);
+  const size_t o_so = img.add(slot_out.data(), slot_out.size() * 4);
+  const size_t o_se = img.add(slot_entry.data(), slot_entry.size() * 4);
+  int rc = B.desc.reserve(img.host.size(), B.device);
+  if (rc) return rc;
+  if (hipMemcpy(B.desc.p, img.host.data(), img.host.size(), hipMemcpyHostToDevice) != hipSuccess) return COEX_EDEVICE;
+  // records
+  const uint64_t NL = std::max<uint64_t>(B.n_lanes, 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o2 = off; off = align_up(off + std::max<size_t>(bytes, 8), 256); return o2; };
+  const size_t r_ctr = take(4), r_fc = take(4), r_err = take(4);
+  const size_t r_fl = take(NL * 4), r_t = take(NL * 4), r_s = take(NL * 4), r_end = take(NL * 4), r_tail = take(NL * 4);
+  size_t r_ts = 0, r_m = 0, r_init = 0, r_ne = 0, r_nc = 0;
+  if (B.needs_nc) {
+    r_ts = take(NL * 4);
+    r_m = take(NL * 4);
+    r_init = take(NL * S.W * 4);
+    r_ne = take(NL * S.W * 4);
+    r_nc = take(NL * S.W * 4);
+  }
+  rc = B.recs.reserve(off, B.device);
+  if (rc) return rc;
+  Args& A = B.args;
+  A = Args{};
+  char* dp = B.desc.p;
+  char* rp = B.recs.p;
+  A.seqs = reinterpret_cast<const SeqD*>(dp + o_seq);
+  A.dfas = reinterpret_cast<const DfaD*>(dp + o_dfa);
+  A.entries = reinterpret_cast<const EntryD*>(dp + o_ent);
+  A.units = reinterpret_cast<const UnitD*>(dp + o_unit);
+  A.groups = reinterpret_cast<const GroupD*>(dp + o_grp);
+  A.slot_dfa = reinterpret_cast<const uint32_t*>(dp + o_sd);
+  A.slot_out = reinterpret_cast<const uint32_t*>(dp + o_so);
+  A.slot_entry = reinterpret_cast<const uint32_t*>(dp + o_se);
+  A.n_groups = (uint32_t)ng;
+  A.n_tasks = B.n_tasks;
+  A.n_slots = B.n_slots;
+  uint32_t tab_max = 0;
+  for (auto& G : S.groups) tab_max = std::max(tab_max, G.tab_bytes);
+  A.bcast_off = tab_max;
+  B.lds_bytes = tab_max + 16;
+  A.chunk = C;
+  A.n_counts = B.n_pairs;
+  A.task_ctr = reinterpret_cast<uint32_t*>(rp + r_ctr);
+  A.fix_count = reinterpret_cast<uint32_t*>(rp + r_fc);
+  A.err = reinterpret_cast<uint32_t*>(rp + r_err);
+  A.fix_list = reinterpret_cast<uint32_t*>(rp + r_fl);
+  A.rec_t = reinterpret_cast<uint32_t*>(rp + r_t);
+  A.rec_s = reinterpret_cast<uint32_t*>(rp + r_s);
+  A.rec_end = reinterpret_cast<uint32_t*>(rp + r_end);
+  A.rec_tail = reinterpret_cast<uint32_t*>(rp + r_tail);
+  if (B.needs_nc) {
+    A.rec_ts = reinterpret_cast<uint32_t*>(rp + r_ts);
+    A.nc_m = reinterpret_cast<uint32_t*>(rp + r_m);
+    A.nc_init = reinterpret_cast<uint32_t*>(rp + r_init);
+    A.nc_end = reinterpret_cast<uint32_t*>(rp + r_ne);
+    A.nc_cnt = reinterpret_cast<uint32_t*>(rp + r_nc);
+  }
+  const uint32_t per_cu = blocks_per_cu(S, e, B.lds_bytes);
+  B.blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)B.n_cu * per_cu, B.n_tasks));
+  // a new layout invalidates a captured graph
+  if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
+  if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
+  return COEX_OK;
+}
+
+int build_batch(const Set* S, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
+                const uint32_t* pair_dfa, uint32_t n_pairs, const coex_opts* o, std::unique_ptr<Batch>& out) {
+  if (!S || (n_seq && !seqs)) return COEX_EINVAL;
+  auto B = std::make_unique<Batch>();
+  B->set = S;
+  if (hipGetDevice(&B->device) != hipSuccess) return COEX_EDEVICE;
+  if (B->device != S->device) return COEX_EINVAL;
+  int rc = device_cus(B->device, B->n_cu);
+  if (rc) return rc;
+  B->flags = o ? o->flags : 0u;
+  B->enc = -1;
+  uint64_t total = 0;
+  B->seqs.resize(n_seq);
+  for (uint32_t s = 0; s < n_seq; ++s) {
+    const coex_seq& q = seqs[s];
+    if (q.encoding != COEX_ENC_BYTE && q.encoding != COEX_ENC_2BIT) return COEX_EINVAL;
+    const int e = q.encoding == COEX_ENC_2BIT ? 1 : 0;
+    if (B->enc < 0) B->enc = e;
+    else if (B->enc != e) return COEX_EINVAL;
+    if (q.n_bases > 0 && !q.bases) return COEX_EINVAL;
+    if (((uintptr_t)q.bases & 15) || ((uintptr_t)q.n_mask & 15)) return COEX_EINVAL;
+    B->seqs[s] = SeqD{reinterpret_cast<const uint8_t*>(q.bases), e == 1 ? q.n_mask : nullptr, q.n_bases};
+  }
+  if (B->enc < 0) B->enc = 0;
+  if (pair_seq || pair_dfa) {
+    if (!pair_seq || !pair_dfa) return COEX_EINVAL;
+    B->pair_seq.assign(pair_seq, pair_seq + n_pairs);
+    B->pair_dfa.assign(pair_dfa, pair_dfa + n_pairs);
+  } else {  // every sequence with every automaton, pair s * n_dfa + d
+    if ((uint64_t)n_seq * S->n_dfa > 0xFFFFFFFFull) return COEX_EINVAL;
+    n_pairs = n_seq * S->n_dfa;
+    B->pair_seq.resize(n_pairs);
+    B->pair_dfa.resize(n_pairs);
+    for (uint32_t s = 0; s < n_seq; ++s)
+      for (uint32_t d = 0; d < S->n_dfa; ++d) {
+        B->pair_seq[s * S->n_dfa + d] = s;
+        B->pair_dfa[s * S->n_dfa + d] = d;
+      }
+  }
+  B->n_pairs = n_pairs;
+  for (uint32_t i = 0; i < n_pairs; ++i) {
+    if (B->pair_seq[i] >= n_seq || B->pair_dfa[i] >= S->n_dfa) return COEX_EINVAL;
+    total += B->seqs[B->pair_seq[i]].n;
+  }
+  if (o && o->chunk) {
+    if (o->chunk < 64) return COEX_EINVAL;
+    B->chunk = o->chunk;
+  } else {
+    B->chunk = default_chunk(*B, total);
+  }
+  // per-chunk tail counters are 32-bit: chunk (at most 2 chunks' bases in the
+  // last one) times the largest weight per base must fit
+  if (2 * B->chunk * 255 > 0xFFFFFFFFull) return COEX_EINVAL;
+  rc = layout(*B);
+  if (rc) return rc;
+  out = std::move(B);
+  return COEX_OK;
+}
+
+int run(Batch& B, uint64_t* counts, hipStream_t st) {
+  if (!counts && B.n_pairs) return COEX_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return COEX_EDEVICE;
+  if (dev != B.device) return COEX_EINVAL;
+  B.args.counts = reinterpret_cast<unsigned long long*>(counts);
+  const bool timed = B.flags & COEX_FLAG_TIME;
+  dispatch(B, st, nullptr, nullptr, true);
+  if (timed && !B.ev0) {
+    if (hipEventCreate(&B.ev0) != hipSuccess || hipEventCreate(&B.ev1) != hipSuccess) return COEX_EDEVICE;
+  }
+  if (B.flags & COEX_FLAG_GRAPH) {
+    if (B.exec && B.graph_counts != B.args.counts) {
+      (void)hipGraphExecDestroy(B.exec);
+      (void)hipGraphDestroy(B.graph);
+      B.exec = nullptr;
+      B.graph = nullptr;
+    }
+    if (!B.exec) {
+      if (!B.cap_stream && hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return COEX_EDEVICE;
+      if (hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return COEX_EDEVICE;
+      dispatch(B, B.cap_stream, nullptr, nullptr);
+      if (hipStreamEndCapture(B.cap_stream, &B.graph) != hipSuccess) return COEX_EDEVICE;
+      if (hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0) != hipSuccess) return COEX_EDEVICE;
+      B.graph_counts = B.args.counts;
+    }
+    if (timed) (void)hipEventRecord(B.ev0, st);
+    if (hipGraphLaunch(B.exec, st) != hipSuccess) return COEX_EDEVICE;
+    if (timed) (void)hipEventRecord(B.ev1, st);
+  } else {
+    dispatch(B, st, timed ? B.ev0 : nullptr, timed ? B.ev1 : nullptr);
+  }
+  if (hipPeekAtLastError() != hipSuccess) return COEX_EDEVICE;
+  B.timed_pending = timed;
+  if (B.flags & COEX_FLAG_CHECK) {
+    uint32_t e = 0;
+    if (hipMemcpyAsync(&e, B.args.err, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return COEX_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return COEX_EDEVICE;
+    if (e) return COEX_EINTERNAL;
+  }
+  return COEX_OK;
+}
+
+}  // namespace batch
+}  // namespace coex
+
+// ====================================================================== C ABI
+extern "C" {
+
+int coex_dfa_set_create(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_opts* opts, coex_dfa_set** out) {
+  if (!out) return COEX_EINVAL;
+  try {
+    std::unique_ptr<coex_dfa_set> S;
+    const int rc = coex::batch::build_set(dfas, n_dfa, opts, S);
+    if (rc) return rc;
+    *out = S.release();
+    return COEX_OK;
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+void coex_dfa_set_free(coex_dfa_set* set) { delete set; }
+
+int coex_batch_create(const coex_dfa_set* set, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
+                      const uint32_t* pair_dfa, uint32_t n_pairs, const coex_opts* opts, coex_batch** out) {
+  if (!out) return COEX_EINVAL;
+  try {
+    std::unique_ptr<coex_batch> B;
+    const int rc = coex::batch::build_batch(set, seqs, n_seq, pair_seq, pair_dfa, n_pairs, opts, B);
+    if (rc) return rc;
+    *out = B.release();
+    return COEX_OK;
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_batch_run(coex_batch* b, uint64_t* counts_dev, void* stream) {
+  if (!b) return COEX_EINVAL;
+  try {
+    return coex::batch::run(*b, counts_dev, (hipStream_t)stream);
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_batch_tune(coex_batch* b, uint64_t* counts_dev, void* stream, uint64_t* chunk_out) {
+  if (!b || !chunk_out) return COEX_EINVAL;
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return COEX_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return COEX_EDEVICE; }
+    const uint32_t keep_flags = b->flags;
+    b->flags &= ~(COEX_FLAG_GRAPH | COEX_FLAG_TIME | COEX_FLAG_CHECK);
+    uint64_t best = b->chunk;
+    float best_ms = 1e30f;
+    int rc = COEX_OK;
+    for (uint64_t c = 4096; c <= (1ull << 20) && rc == COEX_OK; c *= 4) {
+      b->chunk = c;
+      rc = coex::batch::layout(*b);
+      if (rc) break;
+      rc = coex::batch::run(*b, counts_dev, st);  // warm-up
+      if (rc) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = COEX_EDEVICE; break; }
+      rc = coex::batch::run(*b, counts_dev, st);
+      if (rc) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = COEX_EDEVICE; break; }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = COEX_EDEVICE; break; }
+      if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->flags = keep_flags;
+    b->chunk = best;
+    const int rc2 = coex::batch::layout(*b);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    *chunk_out = best;
+    return COEX_OK;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_batch_info(const coex_batch* b, coex_batch_info_t* info) {
+  if (!b || !info) return COEX_EINVAL;
+  const coex_dfa_set& S = *b->set;
+  info->chunk = b->chunk;
+  info->width = S.W;
+  info->step = S.any_step2 ? (S.any_step1 ? 3u : 2u) : 1u;
+  info->n_groups = (uint32_t)S.groups.size();
+  info->n_pairs = b->n_pairs;
+  info->n_tasks = b->n_tasks;
+  info->n_lanes = b->n_lanes;
+  info->blocks = b->blocks;
+  info->last_ms = -1.0;
+  if (b->timed_pending && b->ev1) {
+    if (hipEventSynchronize(b->ev1) != hipSuccess) return COEX_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, b->ev0, b->ev1) != hipSuccess) return COEX_EDEVICE;
+    info->last_ms = ms;
+  }
+  return COEX_OK;
+}
+
+void coex_batch_free(coex_batch* b) { delete b; }
+
+int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_seq* seqs, uint32_t n_seq,
+                       uint64_t* counts_dev, const coex_opts* opts, void* stream) {
+  coex_dfa_set* S = nullptr;
+  int rc = coex_dfa_set_create(dfas, n_dfa, opts, &S);
+  if (rc) return rc;
+  coex_batch* B = nullptr;
+  coex_opts o = opts ? *opts : coex_opts{};
+  o.flags &= ~COEX_FLAG_GRAPH;
+  rc = coex_batch_create(S, seqs, n_seq, nullptr, nullptr, 0, &o, &B);
+  if (rc == COEX_OK) {
+    rc = coex_batch_run(B, counts_dev, stream);
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == COEX_OK) rc = COEX_EDEVICE;
+  }
+  coex_batch_free(B);
+  coex_dfa_set_free(S);
+  return rc;
+}
+
+}  // extern "C"

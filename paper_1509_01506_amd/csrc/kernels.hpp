@@ -581,4 +581,83 @@ __device__ __forceinline__ uint32_t scan_range(const ScanArgs& a, const Tab& tb,
   return scan_blocks<ENC, SHIFT, STEP, false>(a, tb, s, p, hi, sink, unused);
 }
 
+// ------------------------------------------------------------------ chunk headers
+// The 8 bases before `lo` (lo >= 8): table columns two bits per base (oldest
+// first), A,C,G,T codes the same way, and a reset bit per base.
+template <int ENC>
+__device__ __forceinline__ void lookback8(const ScanArgs& a, uint64_t lo, uint32_t& cols, uint32_t& codes,
+                                          uint32_t& rst) {
+  if constexpr (ENC == ENC_2BIT) {
+    if ((lo & 7) == 0) {
+      cols = *reinterpret_cast<const uint16_t*>(a.bases + ((lo - 8) >> 2));
+      rst = a.nmask ? a.nmask[(lo - 8) >> 3] : 0u;
+      codes = cols;
+      return;
+    }
+  } else {
+    if ((lo & 7) == 0) {
+      const uint2 v = *reinterpret_cast<const uint2*>(a.bases + lo - 8);
+      const uint32_t x[2] = {v.x, v.y};
+      cols = codes = rst = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t b = (x[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+        const uint32_t t = (b >> 1) & 3u;
+        const uint32_t expect = (0x47544341u >> (8u * t)) & 0xFFu;
+        rst |= (uint32_t)((b & 0xDFu) != expect) << i;
+        cols |= t << (2 * i);
+        codes |= (t ^ (t >> 1)) << (2 * i);
+      }
+      return;
+    }
+  }
+  cols = codes = rst = 0;
+  for (int i = 0; i < 8; ++i) {
+    const int col = load_col<ENC>(a, lo - 8 + i);
+    if (col < 0) rst |= 1u << i;
+    else {
+      cols |= (uint32_t)col << (2 * i);
+      codes |= col_to_code<ENC>((uint32_t)col) << (2 * i);
+    }
+  }
+}
+
+// Candidate list of the chunk starting at lo: either one exact state (chunk
+// 0, a reset inside the lookback window, or a window that reaches the
+// sequence start) or the PSS table entry of the k-gram before the chunk.
+template <int ENC, int SHIFT>
+__device__ __forceinline__ void chunk_header(const ScanArgs& a, const Tab& tb, const uint32_t* pss_off, uint64_t lo,
+                                             uint32_t& m, uint32_t& cbase, uint32_t& exact, bool& is_exact) {
+  m = 1;
+  cbase = 0;
+  exact = tb.q0s;
+  is_exact = true;
+  if (lo == 0) return;
+  const uint32_t k = a.k;
+  if (lo < 8) {  // the window reaches the sequence start: run from q0
+    uint32_t s = tb.q0s;
+    for (uint64_t i = 0; i < lo; ++i) {
+      const int col = load_col<ENC>(a, i);
+      s = col < 0 ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (uint32_t)col) & 0xFFFFu);
+    }
+    exact = s;
+    return;
+  }
+  uint32_t cols, codes, rst;
+  lookback8<ENC>(a, lo, cols, codes, rst);
+  const uint32_t sh = 8 - k;  // window = the last k of the 8 bases
+  const uint32_t wr = (rst >> sh) & ((1u << k) - 1u);
+  if (wr) {  // a reset inside the window: the state is exact after it
+    uint32_t s = tb.q0s;
+    for (uint32_t i = sh; i < 8; ++i)
+      s = ((rst >> i) & 1u) ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (cols >> (2 * i)) & 3u) & 0xFFFFu);
+    exact = s;
+    return;
+  }
+  const uint32_t idx = (codes >> (2 * sh)) & ((k == 16 ? 0u : (1u << (2 * k))) - 1u);
+  is_exact = false;
+  cbase = pss_off[idx];
+  m = pss_off[idx + 1] - cbase;
+}
+
 }  // namespace coex

@@ -19,7 +19,10 @@ Each function returns host data only; nothing here matches patterns.
 """
 from __future__ import annotations
 
-from . import iid_bytes, markov_2bit, markov_bytes, random_kmers, random_regex
+import numpy as np
+
+from . import (Stream, iid_bytes, lognormal_lengths, loguniform_ints, markov_2bit, markov_bytes, poisson_arrivals,
+               random_kmers, random_regex, uniform_ids)
 
 SMALL_N = 1 << 20
 SMALL_CHUNK = 1 << 16
@@ -47,3 +50,77 @@ def genome_kmers():
 def genome(n: int = GENOME_N):
     packed, mask = markov_2bit(3, n, with_n=True)
     return packed, mask, genome_kmers()
+
+
+# ---------------------------------------------------------------- batched
+BATCH_SEQS = 512
+BATCH_SEED = 4
+BATCH_PATTERN_SEED = 404
+
+
+def kmer_sets(seed: int, count: int, lo: float, hi: float):
+    """`count` random k-mer sets, k in 6..14, with about log-uniform target
+    automaton sizes in [lo, hi] states (count of k-mers = target / k)."""
+    targets = loguniform_ints(seed, 16, count, lo, hi)
+    st = Stream(seed, 17)
+    out = []
+    for i, t in enumerate(targets):
+        k = 6 + st.below(9)
+        out.append(random_kmers(seed * 100 + i, max(1, round((t - 1) / k)), k))
+    return out
+
+
+def regexes(seed: int, count: int):
+    return [random_regex(seed * 100 + 50 + i) for i in range(count)]
+
+
+def batched_patterns():
+    """8 k-mer sets (target sizes log-uniform in [10, 500] states) and 8 random regexes."""
+    return kmer_sets(BATCH_PATTERN_SEED, 8, 10, 500), regexes(BATCH_PATTERN_SEED, 8)
+
+
+def packed_sequences(seed: int, lengths):
+    """One Markov byte buffer (N runs included) holding the sequences back to
+    back, each starting at a multiple of 128 bytes: (buffer, offsets)."""
+    offs, total = [], 0
+    for n in lengths:
+        offs.append(total)
+        total += max(128, (int(n) + 127) // 128 * 128)
+    return markov_bytes(seed, total, with_n=True), offs
+
+
+def batched(count: int = BATCH_SEQS, scale: float = 1.0):
+    """Lengths (log-normal, sigma 1.5, clipped mean about 7.8e6, clipped to
+    [1e4, 5e7]), the packed byte buffer and offsets, and the patterns."""
+    lengths = lognormal_lengths(BATCH_SEED, count)
+    if scale != 1.0:
+        lengths = [max(1, int(n * scale)) for n in lengths]
+    buf, offs = packed_sequences(BATCH_SEED, lengths)
+    return lengths, buf, offs, batched_patterns()
+
+
+# ---------------------------------------------------------------- serving
+SERVE_SEED = 5
+SERVE_PATTERN_SEED = 505
+SERVE_POOL = 100_000_000
+
+
+def serving_patterns():
+    """32 resident automata: 16 k-mer sets (log-uniform [10, 1000] states) and 16 regexes."""
+    return kmer_sets(SERVE_PATTERN_SEED, 16, 10, 1000), regexes(SERVE_PATTERN_SEED, 16)
+
+
+def serving_requests(count: int, qps: float, max_size: float = 1e8):
+    """Arrival times (s), sizes (log-uniform over [1e3, max_size]), automaton
+    ids (uniform over 32) and start offsets into the request pool."""
+    arrivals = poisson_arrivals(SERVE_SEED, count, qps)
+    sizes = loguniform_ints(SERVE_SEED, 18, count, 1e3, max_size)
+    ids = uniform_ids(SERVE_SEED, 19, count, 32)
+    st = Stream(SERVE_SEED, 20)
+    offs = [st.below(max(1, SERVE_POOL - n + 1)) // 16 * 16 for n in sizes]
+    return arrivals, sizes, ids, offs
+
+
+def serving_pool():
+    """The bytes requests are cut from (Markov with N runs, seed 5)."""
+    return markov_bytes(SERVE_SEED, SERVE_POOL + 128, with_n=True)
