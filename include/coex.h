@@ -189,10 +189,11 @@ typedef struct coex_batch coex_batch;
 /* Resident automata: their tables packed into LDS groups on the current
    device (two-symbol rows for automata of at most 1024 states and at most 15
    patterns per state, one-symbol rows for the others; a group holds up to
-   1024 or 4096 states of one kind).  opts may be NULL; opts->width caps the possible starting
-   states a lane runs in lockstep (8 or 16, default 16) and opts->step forces
-   1 or 2 symbols per lookup.  The automata handles must outlive nothing: the
-   set copies what it needs.  Errors: EINVAL, ETOOBIG (an automaton above 4096
+   1024 or 4096 states of one kind).  opts may be NULL; opts->width caps the
+   possible starting states of a chunk (1..64, default 64; a lane runs them in
+   batches of 8 registers, merging each batch into the next at its converging
+   point) and opts->step forces 1 or 2 symbols per lookup.  The set copies
+   what it needs from the automata; they may be freed afterwards.  Errors: EINVAL, ETOOBIG (an automaton above 4096
    states), EUNSUPPORTED (an automaton whose possible starting states exceed
    the width at every lookback k <= 8, or more than 255 patterns per state),
    ENOMEM, EDEVICE. */
@@ -224,7 +225,7 @@ int coex_batch_tune(coex_batch* batch, uint64_t* counts_dev, void* stream, uint6
 
 typedef struct {
   uint64_t chunk;     /* bases per chunk */
-  uint32_t width;     /* candidate registers per lane (8 or 16) */
+  uint32_t width;     /* largest possible-starting-state list of any automaton of the set */
   uint32_t step;      /* symbols per LDS lookup: 1 or 2 (every group), 3 = groups of both kinds */
   uint32_t n_groups;  /* LDS groups of the automaton set */
   uint32_t n_pairs;

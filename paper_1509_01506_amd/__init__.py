@@ -246,6 +246,8 @@ def count(dfa: Dfa, seq: DeviceSeq, out=None, chunk: int = 0, width: int = 0, lo
     P = dfa.info().n_patterns
     if out is None:
         out = torch.empty(max(1, P), dtype=torch.int64, device=seq.bases.device)
+    if out.numel() < P or out.dtype != torch.int64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 tensor of at least %d elements" % P)
     s = seq._c()
     o = _opts(chunk, width, lookback, step, check, timed)
     _check(_lib().coex_count(dfa.handle, ctypes.byref(s), out.data_ptr(), ctypes.byref(o), _stream(stream)),
@@ -301,6 +303,8 @@ def count_batched(dfas: Sequence[Dfa], seqs: Sequence[DeviceSeq], out=None, chun
     ss = (_Seq * len(seqs))(*[s._c() for s in seqs])
     if out is None:
         out = torch.empty((len(seqs), len(dfas)), dtype=torch.int64, device=dev)
+    if out.numel() < len(seqs) * len(dfas) or out.dtype != torch.int64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 tensor of n_seq * n_dfa elements")
     o = _opts(chunk, width, lookback, step)
     _check(_lib().coex_count_batched(ctypes.cast(hs, ctypes.c_void_p), len(dfas), ctypes.cast(ss, ctypes.c_void_p),
                                      len(seqs), out.data_ptr(), ctypes.byref(o), _stream(stream)),
@@ -384,13 +388,18 @@ class Batch:
             out = torch.empty(max(1, self.n_pairs), dtype=torch.int64, device=self.seqs[0].bases.device)
         return out
 
+    def _checked(self, out):
+        if out.numel() < self.n_pairs or out.dtype.itemsize != 8 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous 64-bit tensor of at least %d elements" % self.n_pairs)
+        return out
+
     def run(self, out=None, stream=None):
-        out = self._out(out)
+        out = self._checked(self._out(out))
         _check(_lib().coex_batch_run(self._h, out.data_ptr(), _stream(stream)), "batch_run")
         return out[: self.n_pairs].view(self.shape)
 
     def tune(self, out=None, stream=None) -> int:
-        out = self._out(out)
+        out = self._checked(self._out(out))
         c = ctypes.c_uint64(0)
         _check(_lib().coex_batch_tune(self._h, out.data_ptr(), _stream(stream), ctypes.byref(c)), "batch_tune")
         return int(c.value)

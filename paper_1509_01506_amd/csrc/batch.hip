@@ -104,7 +104,9 @@ struct Args {
   uint32_t* rec_end;   // state at the chunk end
   uint32_t* rec_tail;  // matches after the converging point
   uint32_t* rec_ts;    // true first state (written by k_bcompose)
-  uint32_t* nc_m;      // non-converged chunks: candidates, their end states and counts (lane * W)
+  uint32_t max_cand;   // largest candidate list of any automaton
+  uint32_t nc_stride;  // entries per lane in the arrays below
+  uint32_t* nc_m;      // non-converged chunks: candidates, their end states and counts
   uint32_t* nc_init;
   uint32_t* nc_end;
   uint32_t* nc_cnt;
@@ -132,9 +134,43 @@ __global__ void k_binit(Args A) {
   for (uint32_t i = t; i < A.n_counts; i += gridDim.x * blockDim.x) A.counts[i] = 0;
 }
 
+constexpr int W = 8;  // candidate registers per lane
+
+// One symbol for the active candidate slots; returns whether all slots
+// below n now hold the same state.
+template <int ENC, int SHIFT>
+__device__ __forceinline__ bool step_slots(const Tab& tg, const uint32_t* wtab, uint32_t q0s, int col, uint32_t n,
+                                           uint32_t lo_slot, uint32_t (&cand)[W], uint32_t (&pc)[W]) {
+  bool same = true;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    if (i < (int)n && i >= (int)lo_slot) {
+      uint32_t s2 = q0s;
+      if (col >= 0) {
+        const uint32_t e = t1_lookup<SHIFT>(tg, cand[i], (uint32_t)col);
+        s2 = e & 0xFFFFu;
+        if (e >> 16) pc[i] += wtab[(e >> 16) - 1u];
+      }
+      cand[i] = s2;
+    }
+    if (i < (int)n) same = same && cand[i] == cand[0];
+  }
+  return same;
+}
+
 // One (chunk, automaton) pair: candidates, lockstep speculation, the scan
 // after the converging point, and the chunk's records.
-template <int ENC, int SHIFT, int STEP, int W>
+//
+// The candidates run in batches of at most 8 registers.  The first batch
+// runs from the chunk start until its states agree (the converging point
+// of those runs); that state becomes the representative of every candidate
+// seen so far and takes slot 0 of the next batch, which runs its new
+// candidates from the chunk start and the representative from its
+// converging point on, until all agree again.  After the last batch every
+// candidate's run has reached one state: the chunk's converging point.
+// Counts: the candidates agree on the prefix count iff every batch's slots
+// agreed at its converging point (counts after a common state are common).
+template <int ENC, int SHIFT, int STEP>
 __device__ __forceinline__ void lane_scan(const Args& A, const GroupD& G, const char* lds, uint64_t gl, uint64_t L) {
   const uint32_t D = G.D;
   const UnitD un = A.units[G.unit0 + L / D];
@@ -156,75 +192,87 @@ __device__ __forceinline__ void lane_scan(const Args& A, const GroupD& G, const 
   uint32_t m, cbase, exact;
   bool is_exact;
   chunk_header<ENC, SHIFT>(sa, tg, df.pss_off, lo, m, cbase, exact, is_exact);
-  if (m == 0 || m > (uint32_t)W) {
+  if (m == 0 || m > A.max_cand) {
     atomicOr(A.err, 1u);
     return;
   }
-  uint32_t cand[W], pc[W];
-#pragma unroll
-  for (int i = 0; i < W; ++i) {
-    cand[i] = 0;
-    pc[i] = 0;
-    if (i < (int)m) cand[i] = is_exact ? exact : df.base + ((uint32_t)df.pss_states[cbase + i] << SHIFT);
-  }
-  // lockstep runs of the candidates until they agree
-  uint64_t p = lo;
-  bool conv = m == 1;
-  while (!conv && p < hi) {
-    const int col = load_col<ENC>(sa, p);
-    bool same = true;
+  uint32_t rep = exact, rep_cnt = 0;
+  uint64_t T = lo;
+  bool have_rep = is_exact, eq = true, conv = true;
+  for (uint32_t next = is_exact ? m : 0u; next < m;) {
+    const uint32_t off = have_rep ? 1u : 0u;
+    const uint32_t k = min(m - next, (uint32_t)W - off);
+    const uint32_t n = k + off;
+    uint32_t cand[W], pc[W];
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      if (i < (int)m) {
-        uint32_t s2 = df.q0s;
-        if (col >= 0) {
-          const uint32_t e = t1_lookup<SHIFT>(tg, cand[i], (uint32_t)col);
-          s2 = e & 0xFFFFu;
-          if (e >> 16) pc[i] += G.wtab[(e >> 16) - 1u];
-        }
-        cand[i] = s2;
-        same = same && s2 == cand[0];
+      cand[i] = 0;
+      pc[i] = 0;
+      if (i < (int)off) {
+        cand[i] = rep;
+        pc[i] = rep_cnt;
+      } else if (i < (int)n) {
+        cand[i] = df.base + ((uint32_t)df.pss_states[cbase + next + (uint32_t)i - off] << SHIFT);
       }
     }
-    ++p;
-    conv = same;
+    uint64_t p = lo;
+    conv = n == 1;  // a single run is its own converging point
+    // new candidates alone up to the representative's position
+    for (; p < T; ++p) step_slots<ENC, SHIFT>(tg, G.wtab, df.q0s, load_col<ENC>(sa, p), n, off, cand, pc);
+    while (!conv && p < hi) {
+      conv = step_slots<ENC, SHIFT>(tg, G.wtab, df.q0s, load_col<ENC>(sa, p), n, 0u, cand, pc);
+      ++p;
+    }
+    if (!conv) break;
+#pragma unroll
+    for (int i = 1; i < W; ++i)
+      if (i < (int)n) eq = eq && pc[i] == pc[0];
+    rep = cand[0];
+    rep_cnt = pc[0];
+    T = p;
+    have_rep = true;
+    next += k;
   }
   if (!conv && !A.nc_m) {  // cannot happen when the chunk exceeds every synchronising depth
     atomicOr(A.err, 8u);
     A.rec_t[gl] = 0;
-    A.rec_end[gl] = cand[0];
+    A.rec_end[gl] = rep;
     return;
   }
-  if (!conv) {  // the chunk's state map on its candidates
+  if (!conv) {  // the chunk's state map on its candidates: each run to the chunk end
     A.rec_t[gl] = NONCONV;
     A.nc_m[gl] = m;
+    for (uint32_t next = 0; next < m; next += W) {
+      const uint32_t n = min(m - next, (uint32_t)W);
+      uint32_t cand[W], pc[W];
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      if (i < (int)m) {
-        const uint64_t x = gl * W + i;
-        A.nc_init[x] = df.base + ((uint32_t)df.pss_states[cbase + i] << SHIFT);
-        A.nc_end[x] = cand[i];
-        A.nc_cnt[x] = pc[i];
+      for (int i = 0; i < W; ++i) {
+        pc[i] = 0;
+        cand[i] = i < (int)n ? df.base + ((uint32_t)df.pss_states[cbase + next + (uint32_t)i] << SHIFT) : 0u;
+      }
+      for (uint64_t p = lo; p < hi; ++p) step_slots<ENC, SHIFT>(tg, G.wtab, df.q0s, load_col<ENC>(sa, p), n, 0u, cand, pc);
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        if (i < (int)n) {
+          const uint64_t x = gl * A.nc_stride + next + i;
+          A.nc_init[x] = df.base + ((uint32_t)df.pss_states[cbase + next + (uint32_t)i] << SHIFT);
+          A.nc_end[x] = cand[i];
+          A.nc_cnt[x] = pc[i];
+        }
       }
     }
     return;
   }
-  bool common = true;
-#pragma unroll
-  for (int i = 1; i < W; ++i)
-    if (i < (int)m) common = common && pc[i] == pc[0];
-  const uint32_t s0 = cand[0];
-  const uint32_t prefix = pc[0];
   const Tab tb{lds, STEP == 2 ? reinterpret_cast<const char*>(G.t1) : lds, df.q0s};
   SinkTotal sink{G.wtab};
-  const uint32_t e_end = scan_range<ENC, SHIFT, STEP>(sa, tb, s0, p, hi, sink);
+  const uint32_t e_end = scan_range<ENC, SHIFT, STEP>(sa, tb, rep, T, hi, sink);
   A.rec_end[gl] = e_end;
-  A.rec_t[gl] = (uint32_t)(p - lo);
-  if (common) {
-    const uint64_t tot = (uint64_t)prefix + sink.cnt;
+  A.rec_t[gl] = (uint32_t)(T - lo);
+  if (eq) {
+    const uint64_t tot = (uint64_t)rep_cnt + sink.cnt;
     if (tot) atomicAdd(A.counts + A.slot_out[slot], (unsigned long long)tot);
   } else {
-    A.rec_s[gl] = s0;
+    A.rec_s[gl] = rep;
     A.rec_tail[gl] = sink.cnt;
     A.fix_list[atomicAdd(A.fix_count, 1u)] = (uint32_t)gl;
   }
@@ -233,8 +281,8 @@ __device__ __forceinline__ void lane_scan(const Args& A, const GroupD& G, const 
 // Persistent scan: every block takes 768-lane tasks until the counter passes
 // the last one (every wave reaches the exit).  LDS holds the group image at
 // address 0 and one broadcast word after it.
-template <int ENC, int W>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W == 8 ? COEX_TAIL_WAVES : 4, 8))) void k_bscan(Args A) {
+template <int ENC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(COEX_TAIL_WAVES, 8))) void k_bscan(Args A) {
   extern __shared__ __align__(16) char lds[];
   uint32_t* bc = reinterpret_cast<uint32_t*>(lds + A.bcast_off);
   if (threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(A.err, 64u);
@@ -262,8 +310,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W == 8 ?
     __syncthreads();
     const uint64_t L = (uint64_t)(task - G.task0) * kBlock + threadIdx.x;
     if (L < G.n_lanes) {
-      if (G.step == 2) lane_scan<ENC, 6, 2, W>(A, G, lds, G.lane0 + L, L);
-      else lane_scan<ENC, 4, 1, W>(A, G, lds, G.lane0 + L, L);
+      if (G.step == 2) lane_scan<ENC, 6, 2>(A, G, lds, G.lane0 + L, L);
+      else lane_scan<ENC, 4, 1>(A, G, lds, G.lane0 + L, L);
     }
     __syncthreads();
   }
@@ -273,7 +321,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W == 8 ?
 // walks its chunks in order, picking each non-converged chunk's map entry
 // for the true first state and recording the true first state of the
 // others for the fix-up.
-template <int W>
 __global__ void k_bcompose(Args A) {
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= A.n_slots) return;
@@ -290,13 +337,14 @@ __global__ void k_bcompose(Args A) {
     if (A.rec_t[gl] == NONCONV) {
       const uint32_t m = A.nc_m[gl];
       uint32_t i = 0;
-      while (i < m && A.nc_init[gl * W + i] != q) ++i;
+      const uint64_t b0 = gl * A.nc_stride;
+      while (i < m && A.nc_init[b0 + i] != q) ++i;
       if (i == m) {
         atomicOr(A.err, 4u);
         return;
       }
-      add += A.nc_cnt[gl * W + i];
-      q = A.nc_end[gl * W + i];
+      add += A.nc_cnt[b0 + i];
+      q = A.nc_end[b0 + i];
     } else {
       A.rec_ts[gl] = q;
       q = A.rec_end[gl];
@@ -477,11 +525,8 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
   S->n_dfa = n_dfa;
   std::vector<const Dfa*> ds(n_dfa);
   std::vector<uint32_t> step_of(n_dfa, 2);
-  uint32_t wmax = (o && o->width) ? o->width : 16u;
-  if (wmax != 1 && wmax != 8 && wmax != 16) {
-    if (wmax > 16) return COEX_EUNSUPPORTED;
-    wmax = wmax <= 8 ? 8u : 16u;
-  }
+  const uint32_t wmax = (o && o->width) ? o->width : 64u;
+  if (wmax > 64) return COEX_EINVAL;
   for (uint32_t i = 0; i < n_dfa; ++i) {
     if (!hs[i]) return COEX_EINVAL;
     ds[i] = reinterpret_cast<const Dfa*>(hs[i]);
@@ -495,7 +540,7 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
     (step_of[i] == 2 ? S->any_step2 : S->any_step1) = true;
   }
   // lookback per automaton: the shortest whose largest candidate list fits
-  // the width (8 if possible, else the width asked for)
+  // one batch of registers (8), else the one with the fewest candidates
   S->k_of.resize(n_dfa);
   uint32_t W = 1;
   for (uint32_t i = 0; i < n_dfa; ++i) {
@@ -503,15 +548,19 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
     uint32_t k = 0;
     for (uint32_t kk = 1; kk <= kMaxLookback && !k; ++kk)
       if (d.pss[kk].max_size <= std::min<uint32_t>(8, wmax)) k = kk;
-    for (uint32_t kk = 1; kk <= kMaxLookback && !k; ++kk)
-      if (d.pss[kk].max_size <= wmax) k = kk;
+    if (!k) {
+      uint32_t best = kMaxLookback;
+      for (uint32_t kk = 1; kk <= kMaxLookback; ++kk)
+        if (d.pss[kk].max_size < d.pss[best].max_size) best = kk;
+      if (d.pss[best].max_size <= wmax) k = best;
+    }
     if (!k) return COEX_EUNSUPPORTED;
     S->k_of[i] = k;
     W = std::max(W, d.pss[k].max_size);
     if (d.sync_depth == kNoSync) S->may_not_converge_below = true;
     else S->max_sync = std::max(S->max_sync, d.sync_depth + k);
   }
-  S->W = W <= 8 ? 8u : 16u;
+  S->W = W;  // largest candidate list
   // groups: first fit by decreasing size among automata of the same step
   std::vector<uint32_t> order(n_dfa);
   for (uint32_t i = 0; i < n_dfa; ++i) order[i] = i;
@@ -619,18 +668,18 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
   return COEX_OK;
 }
 
-template <int ENC, int W>
+template <int ENC>
 int occupancy(uint32_t lds) {
   int b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bscan<ENC, W>, kBlock, lds) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bscan<ENC>, kBlock, lds) != hipSuccess) return 1;
   return std::max(1, b);
 }
 
-template <int ENC, int W>
+template <int ENC>
 void launch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs_only) {
   Args& A = B.args;
   if (attrs_only) {
-    (void)hipFuncSetAttribute((const void*)k_bscan<ENC, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_bscan<ENC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)B.lds_bytes);
     return;
   }
@@ -638,10 +687,10 @@ void launch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs_o
                      dim3(256), 0, st, A);
   if (B.n_tasks) {
     if (e0) (void)hipEventRecord(e0, st);
-    hipLaunchKernelGGL((k_bscan<ENC, W>), dim3(B.blocks), dim3(kBlock), B.lds_bytes, st, A);
+    hipLaunchKernelGGL((k_bscan<ENC>), dim3(B.blocks), dim3(kBlock), B.lds_bytes, st, A);
     if (e1) (void)hipEventRecord(e1, st);
     if (B.needs_nc)
-      hipLaunchKernelGGL(k_bcompose<W>, dim3((B.n_slots + 255) / 256), dim3(256), 0, st, A);
+      hipLaunchKernelGGL(k_bcompose, dim3((B.n_slots + 255) / 256), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_bfix<ENC>, dim3(std::max(1, B.n_cu)), dim3(256), 0, st, A);
   }
 }
@@ -651,20 +700,20 @@ void dispatch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs
   const Set& S = *B.set;
   const bool by = B.enc == 0;
   const bool a = attrs_only;
-  if (S.W == 8) by ? launch<ENC_BYTE, 8>(B, st, e0, e1, a) : launch<ENC_2BIT, 8>(B, st, e0, e1, a);
-  else by ? launch<ENC_BYTE, 16>(B, st, e0, e1, a) : launch<ENC_2BIT, 16>(B, st, e0, e1, a);
+  (void)S;
+  by ? launch<ENC_BYTE>(B, st, e0, e1, a) : launch<ENC_2BIT>(B, st, e0, e1, a);
 }
 
 uint32_t blocks_per_cu(const Set& S, int enc, uint32_t lds) {
   static std::mutex mu;
   static std::map<std::tuple<int, uint32_t, uint32_t>, int> cache;
-  const auto key = std::make_tuple(enc, S.W, lds);
+  const auto key = std::make_tuple(enc, 0u, lds);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return (uint32_t)it->second;
   const bool by = enc == 0;
-  const int b = S.W == 8 ? (by ? occupancy<ENC_BYTE, 8>(lds) : occupancy<ENC_2BIT, 8>(lds))
-                         : (by ? occupancy<ENC_BYTE, 16>(lds) : occupancy<ENC_2BIT, 16>(lds));
+  (void)S;
+  const int b = by ? occupancy<ENC_BYTE>(lds) : occupancy<ENC_2BIT>(lds);
   cache[key] = b;
   return (uint32_t)b;
 }
@@ -783,6 +832,8 @@ int layout(Batch& B) {
   A.bcast_off = tab_max;
   B.lds_bytes = tab_max + 16;
   A.chunk = C;
+  A.max_cand = S.W;
+  A.nc_stride = S.W;
   A.n_counts = B.n_pairs;
   A.task_ctr = reinterpret_cast<uint32_t*>(rp + r_ctr);
   A.fix_count = reinterpret_cast<uint32_t*>(rp + r_fc);

@@ -128,9 +128,9 @@ def test_widths_steps_and_groups(coex):
     pats = _pats(coex) + [Pat(coex, "kmers", synth.random_kmers(66 + i, 60, 12)) for i in range(3)]
     dev, host = _seqs(coex, 73, LENGTHS[3:], coex.ENC_BYTE)
     exp = _expect(pats, host)
-    for width, step in [(8, 0), (16, 1), (0, 2)]:
+    for width, step in [(8, 0), (64, 1), (0, 2), (16, 0)]:
         # width 8 takes the automata whose candidate lists fit 8 at some lookback
-        use = [i for i, p in enumerate(pats) if width != 8 or min(p.dfa.info().max_pss[1:]) <= 8]
+        use = [i for i, p in enumerate(pats) if min(p.dfa.info().max_pss[1:]) <= (width or 64)]
         assert len(use) >= 5
         dset = coex.DfaSet([pats[i].dfa for i in use], width=width, step=step)
         b = coex.Batch(dset, dev, chunk=5000, check=True)
