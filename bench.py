@@ -92,6 +92,14 @@ def build_workload(name: str):
                     desc="batched: 512 Markov byte sequences (log-normal lengths, sigma 1.5, clipped to [1e4, 5e7], "
                          "%d bases) x 16 automata (8 random k-mer sets, 8 random regexes); per-pair counts; "
                          "one persistent launch replayed as a HIP graph" % int(sum(lengths)))
+    if name == "serving":
+        sets, rxs = configs.serving_patterns()
+        dfas = [coex.Dfa.kmers(k) for k in sets] + [coex.Dfa.regex(r) for r in rxs]
+        return dict(n=0, dfas=dfas, sets=sets, rxs=rxs,
+                    desc="serving: Poisson arrivals; sizes log-uniform over [1e3, 1e8] bases (Markov bytes, "
+                         "1%% N runs); automaton ids uniform over 32 resident automata (16 random k-mer sets, "
+                         "16 random regexes, %d-%d states)" % (min(d.info().n_states for d in dfas),
+                                                               max(d.info().n_states for d in dfas)))
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -208,12 +216,116 @@ def bench_batched(args, w):
     print(json.dumps(res), flush=True)
 
 
+def bench_serving(args, w):
+    """Serving workload: the saturated rate of the serving loop (a burst of
+    requests) sets the capacity; two Poisson runs at 0.5 and 0.8 of it give
+    p50/p99 latency, submit to result (copy included) and device-only."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_1509_01506_amd as coex
+    from synth import configs
+    pool_np = configs.serving_pool()
+    pool = torch.from_numpy(pool_np).pin_memory()
+    srv = coex.Server(w["dfas"], hbm_budget=8 << 30)
+
+    def run(arrivals, sizes, ids, offs):
+        tickets = [None] * len(sizes)
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (a, n, d, o) in enumerate(zip(arrivals, sizes, ids, offs)):
+                dt = a - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(pool[o:o + n], d)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        res = []
+        for i in range(len(sizes)):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            res.append(srv.wait(tickets[i]))
+        th.join()
+        wall = time.perf_counter() - t0
+        return res, wall
+
+    # capacity: a burst of requests submitted at once
+    n_burst = 400
+    _, sz, ids, offs = configs.serving_requests(n_burst, 1.0)
+    run([0.0] * n_burst, sz, ids, offs)  # warm-up
+    res, wall = run([0.0] * n_burst, sz, ids, offs)
+    cap_bases = sum(sz) / wall
+    mean_size = (1e8 - 1e3) / np.log(1e8 / 1e3)
+    cap_qps = cap_bases / mean_size
+    log("capacity: %d requests, %.3e bases in %.2f s = %.1f Gbases/s = %.1f requests/s at the mean size"
+        % (n_burst, sum(sz), wall, cap_bases / 1e9, cap_qps))
+    points = {}
+    sample_check = []
+    for load in (0.5, 0.8):
+        qps = load * cap_qps
+        n_req = max(2000, int(qps * 3))
+        arr, sz, ids, offs = configs.serving_requests(n_req, qps)
+        res, wall = run(arr, sz, ids, offs)
+        tot = np.array([r[1]["total_ms"] for r in res])
+        dev = np.array([r[1]["device_ms"] for r in res])
+        l2d = np.array([r[1]["launch_to_done_ms"] for r in res])
+        bs = np.array([r[1]["batch_size"] for r in res])
+        points[str(load)] = {
+            "qps_offered": round(qps, 1), "requests": n_req, "wall_s": round(wall, 2),
+            "gbases_per_s": round(sum(sz) / wall / 1e9, 2),
+            "p50_ms": round(float(np.percentile(tot, 50)), 3), "p99_ms": round(float(np.percentile(tot, 99)), 3),
+            "device_p50_ms": round(float(np.percentile(dev, 50)), 3),
+            "device_p99_ms": round(float(np.percentile(dev, 99)), 3),
+            "launch_to_result_p50_ms": round(float(np.percentile(l2d, 50)), 3),
+            "mean_batch": round(float(bs.mean()), 2)}
+        log("load %.1f: %s" % (load, points[str(load)]))
+        if load == 0.8:
+            order = np.argsort(sz)
+            for i in list(order[: 40]) + list(order[len(order) // 2: len(order) // 2 + 40]) + list(order[-12:]):
+                sample_check.append((int(offs[i]), int(sz[i]), int(ids[i]), res[i][0]))
+    st = srv.stats()
+    srv.close()
+    p8 = points["0.8"]
+    result = {
+        "metric": "Gbases/s served and p50/p99 latency (exact counts)",
+        "value": p8["gbases_per_s"], "unit": "Gbases/s",
+        "n_gpus": 1, "steps": 2, "warmup": 1, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": w["desc"], "capacity_requests_per_s": round(cap_qps, 1),
+                   "capacity_gbases_per_s": round(cap_bases / 1e9, 2), "hbm_budget_bytes": 8 << 30,
+                   "parallelism": "single GPU"},
+        "latency": points, "server": {"batches": st["n_batches"], "requests": st["n_done"],
+                                      "max_arena_bytes": st["max_arena_bytes"]},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        regs = [oracle.Regex(r) for r in w["rxs"]]
+        nk = len(w["sets"])
+        t0 = time.perf_counter()
+        exact, bases = True, 0
+        for o, n, d, got in sample_check:
+            h = oracle.byte_seq(pool_np[o:o + n])
+            e = int(oracle.count_kmers(w["sets"][d], h)[0].sum()) if d < nk else int(regs[d - nk].scan(h)[0])
+            exact &= e == got
+            bases += n
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(bases / dt / 1e9, 4), "unit": "Gbases/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": "%d requests of the 0.8 run (%d bases), one thread, %.1f s"
+                                            % (len(sample_check), bases, dt)}
+        result["exact"] = bool(exact)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small", "batched"])
+    ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small", "batched", "serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (scale for rocprofv3 byte counters)")
@@ -244,6 +356,8 @@ def main():
     log("workload generated in %.1f s" % (time.perf_counter() - t0))
     if args.workload == "batched":
         return bench_batched(args, w)
+    if args.workload == "serving":
+        return bench_serving(args, w)
     data, mask = w["host"]
     seq = coex.to_device(data, n=w["n"], encoding=w["enc"], nmask=mask)
     dfa = w["dfa"]

@@ -212,6 +212,12 @@ void coex_dfa_set_free(coex_dfa_set* set);
 int coex_batch_create(const coex_dfa_set* set, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
                       const uint32_t* pair_dfa, uint32_t n_pairs, const coex_opts* opts, coex_batch** out);
 
+/* Points the batch at new sequences and pairs (same rules as
+   coex_batch_create), reusing its device buffers when they are large enough.
+   The batch must not be running.  Synchronous (uploads descriptors). */
+int coex_batch_update(coex_batch* batch, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
+                      const uint32_t* pair_dfa, uint32_t n_pairs);
+
 /* Runs the batch: counts_dev uint64[n_pairs] receives the total number of
    matches (all pattern ids) of each pair.  Asynchronous on `stream` unless
    COEX_FLAG_CHECK was given.  Runs of one batch must not overlap. */
@@ -243,6 +249,65 @@ void coex_batch_free(coex_batch* batch);
    `stream`. */
 int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_seq* seqs, uint32_t n_seq,
                        uint64_t* counts_dev, const coex_opts* opts, void* stream);
+
+/* ------------------------------------------------------------ serving
+   A serving loop over resident automata: requests (one host sequence of
+   ASCII bases and one automaton index each) are admitted in arrival order
+   into a device arena of `hbm_budget` bytes, copied on a copy stream while
+   earlier batches run, and every admitted request whose copy has finished is
+   launched in the next batch (continuous batching; up to two batches queued
+   on the compute stream).  A request's count is its pair's count in a batch,
+   so it is the same alone or in any mix.  One worker thread per server;
+   submit and wait may be called from any thread. */
+
+typedef struct coex_server coex_server;
+
+typedef struct {
+  uint64_t hbm_budget;  /* bytes of device memory for admitted sequences (0 = 4 GiB) */
+  uint32_t max_batch;   /* requests per launch (0 = 1024) */
+  uint32_t chunk;       /* bases per chunk (0 = chosen per batch) */
+  uint32_t width;       /* as coex_dfa_set_create */
+  uint32_t flags;       /* reserved, 0 */
+} coex_server_opts;
+
+typedef struct {
+  double queue_ms;          /* submit -> admitted (arena space granted, copy queued) */
+  double h2d_ms;            /* device time of the host-to-device copy */
+  double device_ms;         /* device time of the request's batch (launch to counts copied back) */
+  double total_ms;          /* submit -> result available on the host */
+  double launch_to_done_ms; /* batch launch -> result available (host clock) */
+  uint32_t batch_size;      /* requests in the request's batch */
+} coex_request_stats_t;
+
+typedef struct {
+  uint64_t n_submitted, n_done, n_batches, bases_done;
+  uint64_t arena_bytes, max_arena_bytes;
+  double device_ms;         /* summed device time of finished batches */
+} coex_server_stats_t;
+
+/* Creates a server on the current device over a copy of the automata (the
+   handles may be freed afterwards) and starts its worker thread.  opts may be
+   NULL.  Errors: as coex_dfa_set_create, ENOMEM for the arena. */
+int coex_server_create(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_server_opts* opts,
+                       coex_server** out);
+
+/* Queues one request.  host_bases (n_bases ASCII bytes) must stay valid and
+   unchanged until coex_server_wait returns for the ticket; page-locked
+   memory lets its copy overlap running batches.  Never blocks on the GPU.
+   Errors: EINVAL (bad automaton index or NULL pointer). */
+int coex_server_submit(coex_server* server, const void* host_bases, uint64_t n_bases, uint32_t dfa,
+                       uint64_t* ticket);
+
+/* Blocks until the request is done; *count receives its number of matches
+   (all pattern ids) and *stats (may be NULL) its latencies.  Each ticket is
+   waited for once.  Returns the request's status (ENOMEM if it can never fit
+   the arena, EDEVICE on a runtime error). */
+int coex_server_wait(coex_server* server, uint64_t ticket, uint64_t* count, coex_request_stats_t* stats);
+
+int coex_server_stats(coex_server* server, coex_server_stats_t* stats);
+
+/* Finishes every queued request, stops the worker and frees the server. */
+void coex_server_free(coex_server* server);
 
 const char* coex_strerror(int status);
 

@@ -29,8 +29,9 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_find", "coex_count_chunks",
             "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
-            "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free", "coex_profile",
-            "coex_strerror", "coex_version"]
+            "coex_batch_update", "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free",
+            "coex_server_create", "coex_server_submit", "coex_server_wait", "coex_server_stats", "coex_server_free",
+            "coex_profile", "coex_strerror", "coex_version"]
 
 
 class CoexError(RuntimeError):
@@ -64,7 +65,25 @@ class _BatchInfo(ctypes.Structure):
 
 
 _L = None
-_VOID = ("coex_dfa_free", "coex_strerror", "coex_version", "coex_dfa_set_free", "coex_batch_free")
+_VOID = ("coex_dfa_free", "coex_strerror", "coex_version", "coex_dfa_set_free", "coex_batch_free",
+         "coex_server_free")
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("width", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class _ReqStats(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("h2d_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("launch_to_done_ms", ctypes.c_double),
+                ("batch_size", ctypes.c_uint32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("n_submitted", ctypes.c_uint64), ("n_done", ctypes.c_uint64), ("n_batches", ctypes.c_uint64),
+                ("bases_done", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("max_arena_bytes", ctypes.c_uint64), ("device_ms", ctypes.c_double)]
 
 
 def _lib():
@@ -90,7 +109,14 @@ def _lib():
         L.coex_dfa_set_free.argtypes = [p]
         L.coex_dfa_set_free.restype = None
         L.coex_batch_create.argtypes = [p, p, u32, p, p, u32, p, p]
+        L.coex_batch_update.argtypes = [p, p, u32, p, p, u32]
         L.coex_batch_run.argtypes = [p, p, p]
+        L.coex_server_create.argtypes = [p, u32, p, p]
+        L.coex_server_submit.argtypes = [p, p, u64, u32, p]
+        L.coex_server_wait.argtypes = [p, u64, p, p]
+        L.coex_server_stats.argtypes = [p, p]
+        L.coex_server_free.argtypes = [p]
+        L.coex_server_free.restype = None
         L.coex_batch_tune.argtypes = [p, p, p, p]
         L.coex_batch_info.argtypes = [p, p]
         L.coex_batch_free.argtypes = [p]
@@ -418,6 +444,63 @@ class Batch:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop over resident automata (coex_server): submit host
+    sequences (ASCII bytes; page-locked tensors copy asynchronously) with an
+    automaton index, wait for counts and per-request latencies."""
+
+    def __init__(self, dfas: Sequence[Dfa], hbm_budget: int = 0, max_batch: int = 0, chunk: int = 0,
+                 width: int = 0):
+        hs = (ctypes.c_void_p * len(dfas))(*[d.handle.value for d in dfas])
+        o = _ServerOpts(int(hbm_budget), int(max_batch), int(chunk), int(width), 0)
+        out = ctypes.c_void_p()
+        _check(_lib().coex_server_create(ctypes.cast(hs, ctypes.c_void_p), len(dfas), ctypes.byref(o),
+                                         ctypes.byref(out)), "server_create")
+        self._h = out
+        self._keep = {}
+
+    def submit(self, data, dfa: int) -> int:
+        """data: a CPU torch.uint8 tensor or a numpy uint8 array (kept alive until wait)."""
+        if isinstance(data, np.ndarray):
+            arr = np.ascontiguousarray(data, dtype=np.uint8)
+            ptr, n = arr.ctypes.data, arr.size
+        else:
+            arr = data.contiguous()
+            ptr, n = arr.data_ptr(), arr.numel()
+        t = ctypes.c_uint64(0)
+        _check(_lib().coex_server_submit(self._h, ptr if n else None, n, int(dfa), ctypes.byref(t)), "server_submit")
+        self._keep[t.value] = arr
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(count, stats dict) of a submitted request."""
+        c = ctypes.c_uint64(0)
+        st = _ReqStats()
+        rc = _lib().coex_server_wait(self._h, int(ticket), ctypes.byref(c), ctypes.byref(st))
+        self._keep.pop(int(ticket), None)
+        _check(rc, "server_wait")
+        return int(c.value), {"queue_ms": st.queue_ms, "h2d_ms": st.h2d_ms, "device_ms": st.device_ms,
+                              "total_ms": st.total_ms, "launch_to_done_ms": st.launch_to_done_ms,
+                              "batch_size": st.batch_size}
+
+    def stats(self) -> dict:
+        x = _ServerStats()
+        _check(_lib().coex_server_stats(self._h, ctypes.byref(x)), "server_stats")
+        return {k: getattr(x, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib().coex_server_free(self._h)
+            self._h = ctypes.c_void_p(0)
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

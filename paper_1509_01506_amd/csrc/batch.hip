@@ -485,7 +485,7 @@ struct coex_dfa_set {
 struct coex_batch {
   const coex_dfa_set* set = nullptr;
   int device = 0, n_cu = 0, enc = 0;
-  uint64_t chunk = 0;
+  uint64_t chunk = 0, fixed_chunk = 0;
   uint32_t n_pairs = 0, flags = 0, blocks = 0, lds_bytes = 0;
   bool needs_nc = false;
   // host descriptors (kept to rebuild with another chunk length)
@@ -858,9 +858,57 @@ int layout(Batch& B) {
   return COEX_OK;
 }
 
+// Validates sequences and pairs, then lays the batch out for them (a failed
+// call leaves the batch as it was).
+int set_work(Batch& B, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq, const uint32_t* pair_dfa,
+             uint32_t n_pairs) {
+  const Set* S = B.set;
+  if (n_seq && !seqs) return COEX_EINVAL;
+  int enc = -1;
+  std::vector<SeqD> sv(n_seq);
+  for (uint32_t s = 0; s < n_seq; ++s) {
+    const coex_seq& q = seqs[s];
+    if (q.encoding != COEX_ENC_BYTE && q.encoding != COEX_ENC_2BIT) return COEX_EINVAL;
+    const int e = q.encoding == COEX_ENC_2BIT ? 1 : 0;
+    if (enc < 0) enc = e;
+    else if (enc != e) return COEX_EINVAL;
+    if (q.n_bases > 0 && !q.bases) return COEX_EINVAL;
+    if (((uintptr_t)q.bases & 15) || ((uintptr_t)q.n_mask & 15)) return COEX_EINVAL;
+    sv[s] = SeqD{reinterpret_cast<const uint8_t*>(q.bases), e == 1 ? q.n_mask : nullptr, q.n_bases};
+  }
+  std::vector<uint32_t> ps, pd;
+  if (pair_seq || pair_dfa) {
+    if (!pair_seq || !pair_dfa) return COEX_EINVAL;
+    ps.assign(pair_seq, pair_seq + n_pairs);
+    pd.assign(pair_dfa, pair_dfa + n_pairs);
+  } else {  // every sequence with every automaton, pair s * n_dfa + d
+    if ((uint64_t)n_seq * S->n_dfa > 0xFFFFFFFFull) return COEX_EINVAL;
+    n_pairs = n_seq * S->n_dfa;
+    ps.resize(n_pairs);
+    pd.resize(n_pairs);
+    for (uint32_t s = 0; s < n_seq; ++s)
+      for (uint32_t d = 0; d < S->n_dfa; ++d) {
+        ps[s * S->n_dfa + d] = s;
+        pd[s * S->n_dfa + d] = d;
+      }
+  }
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < n_pairs; ++i) {
+    if (ps[i] >= n_seq || pd[i] >= S->n_dfa) return COEX_EINVAL;
+    total += sv[ps[i]].n;
+  }
+  B.enc = enc < 0 ? 0 : enc;
+  B.seqs.swap(sv);
+  B.pair_seq.swap(ps);
+  B.pair_dfa.swap(pd);
+  B.n_pairs = n_pairs;
+  B.chunk = B.fixed_chunk ? B.fixed_chunk : default_chunk(B, total);
+  return layout(B);
+}
+
 int build_batch(const Set* S, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
                 const uint32_t* pair_dfa, uint32_t n_pairs, const coex_opts* o, std::unique_ptr<Batch>& out) {
-  if (!S || (n_seq && !seqs)) return COEX_EINVAL;
+  if (!S) return COEX_EINVAL;
   auto B = std::make_unique<Batch>();
   B->set = S;
   if (hipGetDevice(&B->device) != hipSuccess) return COEX_EDEVICE;
@@ -868,50 +916,13 @@ int build_batch(const Set* S, const coex_seq* seqs, uint32_t n_seq, const uint32
   int rc = device_cus(B->device, B->n_cu);
   if (rc) return rc;
   B->flags = o ? o->flags : 0u;
-  B->enc = -1;
-  uint64_t total = 0;
-  B->seqs.resize(n_seq);
-  for (uint32_t s = 0; s < n_seq; ++s) {
-    const coex_seq& q = seqs[s];
-    if (q.encoding != COEX_ENC_BYTE && q.encoding != COEX_ENC_2BIT) return COEX_EINVAL;
-    const int e = q.encoding == COEX_ENC_2BIT ? 1 : 0;
-    if (B->enc < 0) B->enc = e;
-    else if (B->enc != e) return COEX_EINVAL;
-    if (q.n_bases > 0 && !q.bases) return COEX_EINVAL;
-    if (((uintptr_t)q.bases & 15) || ((uintptr_t)q.n_mask & 15)) return COEX_EINVAL;
-    B->seqs[s] = SeqD{reinterpret_cast<const uint8_t*>(q.bases), e == 1 ? q.n_mask : nullptr, q.n_bases};
-  }
-  if (B->enc < 0) B->enc = 0;
-  if (pair_seq || pair_dfa) {
-    if (!pair_seq || !pair_dfa) return COEX_EINVAL;
-    B->pair_seq.assign(pair_seq, pair_seq + n_pairs);
-    B->pair_dfa.assign(pair_dfa, pair_dfa + n_pairs);
-  } else {  // every sequence with every automaton, pair s * n_dfa + d
-    if ((uint64_t)n_seq * S->n_dfa > 0xFFFFFFFFull) return COEX_EINVAL;
-    n_pairs = n_seq * S->n_dfa;
-    B->pair_seq.resize(n_pairs);
-    B->pair_dfa.resize(n_pairs);
-    for (uint32_t s = 0; s < n_seq; ++s)
-      for (uint32_t d = 0; d < S->n_dfa; ++d) {
-        B->pair_seq[s * S->n_dfa + d] = s;
-        B->pair_dfa[s * S->n_dfa + d] = d;
-      }
-  }
-  B->n_pairs = n_pairs;
-  for (uint32_t i = 0; i < n_pairs; ++i) {
-    if (B->pair_seq[i] >= n_seq || B->pair_dfa[i] >= S->n_dfa) return COEX_EINVAL;
-    total += B->seqs[B->pair_seq[i]].n;
-  }
   if (o && o->chunk) {
-    if (o->chunk < 64) return COEX_EINVAL;
-    B->chunk = o->chunk;
-  } else {
-    B->chunk = default_chunk(*B, total);
+    // per-chunk tail counters are 32-bit: the last chunk holds under two
+    // chunks' bases, at most 255 pattern ends per base
+    if (o->chunk < 64 || 2ull * o->chunk * 255 > 0xFFFFFFFFull) return COEX_EINVAL;
+    B->fixed_chunk = o->chunk;
   }
-  // per-chunk tail counters are 32-bit: chunk (at most 2 chunks' bases in the
-  // last one) times the largest weight per base must fit
-  if (2 * B->chunk * 255 > 0xFFFFFFFFull) return COEX_EINVAL;
-  rc = layout(*B);
+  rc = set_work(*B, seqs, n_seq, pair_seq, pair_dfa, n_pairs);
   if (rc) return rc;
   out = std::move(B);
   return COEX_OK;
@@ -1000,6 +1011,18 @@ int coex_batch_create(const coex_dfa_set* set, const coex_seq* seqs, uint32_t n_
   }
 }
 
+int coex_batch_update(coex_batch* b, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
+                      const uint32_t* pair_dfa, uint32_t n_pairs) {
+  if (!b) return COEX_EINVAL;
+  try {
+    return coex::batch::set_work(*b, seqs, n_seq, pair_seq, pair_dfa, n_pairs);
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
 int coex_batch_run(coex_batch* b, uint64_t* counts_dev, void* stream) {
   if (!b) return COEX_EINVAL;
   try {
@@ -1039,6 +1062,7 @@ int coex_batch_tune(coex_batch* b, uint64_t* counts_dev, void* stream, uint64_t*
     (void)hipEventDestroy(e1);
     b->flags = keep_flags;
     b->chunk = best;
+    b->fixed_chunk = best;
     const int rc2 = coex::batch::layout(*b);
     if (rc) return rc;
     if (rc2) return rc2;
