@@ -2,12 +2,12 @@
 //
 // Pipeline of one scan (Section III of the paper, re-laid out for one MI355X):
 //   k_init       clears the small device counters;
-//   k_spec       per tile of 64 chunks (one wave): possible starting states
+//   k_tail       per tile of 64 chunks (one wave): possible starting states
 //                from the lookback table, lockstep speculative runs with
-//                ballot convergence (Algorithm 1's converging point);
-//   k_tail       one lane per chunk: one scan of the rest of the chunk from
-//                the converged state, then the join with the predecessor lane
-//                and the prefix recount inside the wave;
+//                ballot convergence (Algorithm 1's converging point); then one
+//                lane per chunk: one scan of the rest of the chunk from the
+//                converged state, the join with the predecessor lane and the
+//                prefix recount inside the wave;
 //   k_nonconv    chunks that did not converge inside the window: every
 //                candidate runs to the chunk end (the paper's non-converged
 //                runs), giving the chunk's state map on its candidates;
@@ -131,11 +131,12 @@ __device__ __forceinline__ uint32_t run_staged(const Tab& tb, uint32_t s, uint64
 // Speculation for one tile of 64 chunks (one wave): possible starting states
 // from the lookback table, then rounds in which G lanes run the candidates
 // of one chunk in lockstep over its first symbols until they agree (the
-// converging point of Algorithm 1).  Writes conv_t / conv_s per chunk, or
-// queues the chunk as non-converged.
+// converging point of Algorithm 1).  Writes conv_t / conv_s per chunk (and
+// returns this lane's pair), or queues the chunk as non-converged.
 template <int ENC, int SHIFT>
 __device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, const uint32_t* pss_off,
-                                          const uint16_t* pss_states, uint64_t tile_id) {
+                                          const uint16_t* pss_states, uint64_t tile_id, uint32_t& out_t,
+                                          uint32_t& out_s) {
   const int lane = threadIdx.x & 63;
   const uint64_t c = tile_id * TILE + lane;
   const bool valid = c < a.n_chunks;
@@ -188,6 +189,8 @@ __device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, cons
       my_s = rv;
     }
   }
+  out_t = my_t;
+  out_s = my_s;
   if (!valid) return;
   if (my_t == NONCONV) {
     const uint32_t slot = atomicAdd(a.nc_count, 1u);
@@ -198,32 +201,13 @@ __device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, cons
   a.conv_s[c] = my_s;
 }
 
-// LDS: one-symbol table, then the PSS table when it fits.
-template <int ENC, int SHIFT>
-__global__ __launch_bounds__(256) void k_spec(ScanArgs a) {
-  extern __shared__ __align__(16) char lds[];
-  copy_to_lds(lds, a.T1, a.n_states * 16u);
-  const uint32_t* pss_off = a.pss_off;
-  const uint16_t* pss_states = a.pss_states;
-  if (a.spec_pss_off) {
-    uint32_t* po = reinterpret_cast<uint32_t*>(lds + a.spec_pss_off);
-    uint16_t* ps = reinterpret_cast<uint16_t*>(lds + a.spec_pss_states);
-    for (uint32_t i = threadIdx.x; i < a.pss_n_off; i += blockDim.x) po[i] = a.pss_off[i];
-    for (uint32_t i = threadIdx.x; i < a.pss_n_states; i += blockDim.x) ps[i] = a.pss_states[i];
-    pss_off = po;
-    pss_states = ps;
-  }
-  __syncthreads();
-  const Tab tb{nullptr, lds, a.q0s};
-  const uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (t < a.n_tiles) spec_tile<ENC, SHIFT>(a, tb, pss_off, pss_states, t);
-}
-
-// The scan of each chunk from its converging point (one lane per chunk),
-// then the join inside the wave: the predecessor lane's last state is this
-// chunk's true first state, from which the prefix before the converging
-// point is recounted.  The first lane of a wave, non-converged chunks and
-// their successors are left to the fix-up kernel.
+// Speculation, then the scan of each chunk from its converging point (one
+// lane per chunk), then the join inside the wave: the predecessor lane's
+// last state is this chunk's true first state, from which the prefix before
+// the converging point is recounted.  Each wave first runs the speculation
+// of its own 64 chunks (the tile), with the one-symbol table and the PSS
+// table in LDS.  The first lane of a wave, non-converged chunks and their
+// successors are left to the fix-up kernel.
 // HIST: per-final-state visit histogram in LDS (several patterns); else a
 // total with exact two-symbol counts.
 template <int ENC, int SHIFT, int STEP, bool HIST>
@@ -237,6 +221,16 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX
     wl[i] = a.wtab[i];
     if (HIST) hist[i] = 0;
   }
+  const uint32_t* pss_off = a.pss_off;
+  const uint16_t* pss_states = a.pss_states;
+  if (a.spec_pss_off) {
+    uint32_t* po = reinterpret_cast<uint32_t*>(lds + a.spec_pss_off);
+    uint16_t* ps = reinterpret_cast<uint16_t*>(lds + a.spec_pss_states);
+    for (uint32_t i = threadIdx.x; i < a.pss_n_off; i += blockDim.x) po[i] = a.pss_off[i];
+    for (uint32_t i = threadIdx.x; i < a.pss_n_states; i += blockDim.x) ps[i] = a.pss_states[i];
+    pss_off = po;
+    pss_states = ps;
+  }
   __syncthreads();
   const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
   if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
@@ -245,10 +239,8 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = c < a.n_chunks;
   uint32_t my_t = NONCONV, my_s = 0;
-  if (valid) {
-    my_t = a.conv_t[c];
-    my_s = a.conv_s[c];
-  }
+  if ((c >> 6) < a.n_tiles) spec_tile<ENC, SHIFT>(a, Tab{nullptr, tb.t1, a.q0s}, pss_off, pss_states, c >> 6, my_t, my_s);
+  if (!valid) my_t = NONCONV;
   const bool conv = my_t != NONCONV;
   const uint64_t lo = c * a.chunk;
   uint32_t out_e = 0, out_cnt = 0;
@@ -634,7 +626,7 @@ int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) 
 }
 
 struct Plan {
-  uint32_t shift, step, k, group, max_cand, blocks, lds_bytes, spec_lds_bytes;
+  uint32_t shift, step, k, group, max_cand, blocks, lds_bytes;
   uint64_t chunk, n_chunks, n_tiles;
   bool hist;
   int enc;
@@ -642,10 +634,17 @@ struct Plan {
 
 // Bytes of LDS the chunk-scan kernel stages: two-symbol table (step 2),
 // one-symbol table, weights and histogram.
-uint32_t tail_lds_bytes(uint32_t step, const Dfa& d) {
+constexpr uint32_t kPssLdsMax = 16 * 1024;  // larger PSS tables stay in global memory
+
+uint32_t pss_lds_bytes(const Dfa& d, uint32_t k) {
+  const uint32_t b = (uint32_t)align_up(d.pss[k].off.size() * 4, 16) + (uint32_t)align_up(d.pss[k].states.size() * 2, 16);
+  return b <= kPssLdsMax ? b : 0u;
+}
+
+uint32_t tail_lds_bytes(uint32_t step, const Dfa& d, uint32_t k) {
   const uint32_t n = d.n_states;
   const uint32_t acc = (uint32_t)align_up(d.n_accepting * 4, 16);
-  return (step == 2 ? n * 64 : 0) + n * 16 + 2 * acc + 16;
+  return (step == 2 ? n * 64 : 0) + n * 16 + 2 * acc + pss_lds_bytes(d, k) + 16;
 }
 
 template <int ENC, int SHIFT, int STEP, bool HIST>
@@ -661,7 +660,7 @@ int occupancy_of(uint32_t lds) {
 uint32_t tail_blocks_per_cu(const Plan& P, const Dfa& d) {
   static std::mutex mu;
   static std::map<std::tuple<int, uint32_t, uint32_t, bool, uint32_t>, int> cache;
-  const uint32_t lds = tail_lds_bytes(P.step, d);
+  const uint32_t lds = tail_lds_bytes(P.step, d, P.k);
   const auto key = std::make_tuple(P.enc, P.shift, P.step, P.hist, lds);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
@@ -746,12 +745,7 @@ std::pair<hipEvent_t, hipEvent_t>* timing_slot(Workspace* w) {
 template <int ENC, int SHIFT, int STEP, bool HIST>
 void launch_scan(const Plan& P, const ScanArgs& a, int n_cu, hipStream_t st, Workspace* timed) {
   (void)n_cu;
-  // speculation: one wave per tile, 4 tiles per 256-thread block
-  const uint32_t spec_blocks = (uint32_t)std::max<uint64_t>(1, (P.n_tiles + 3) / 4);
-  auto ks = k_spec<ENC, SHIFT>;
-  (void)hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.spec_lds_bytes);
-  hipLaunchKernelGGL(ks, dim3(spec_blocks), dim3(256), P.spec_lds_bytes, st, a);
-  // scan from the converging points: one lane per chunk
+  // speculation and scan: one lane per chunk, one tile of 64 chunks per wave
   auto kt = k_tail<ENC, SHIFT, STEP, HIST>;
   (void)hipFuncSetAttribute((const void*)kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (P.n_chunks + kScanBlock - 1) / kScanBlock);
@@ -816,20 +810,17 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   const uint32_t w_off = t1_off + n * 16;
   const uint32_t h_off = w_off + (uint32_t)align_up(d.n_accepting * 4, 16);
   uint32_t lds_end = h_off + (uint32_t)align_up(d.n_accepting * 4, 16);
-  // the PSS table of the chosen lookback goes to LDS when it is small
+  // the PSS table of the chosen lookback goes to LDS (after the histogram)
+  // when it is small
   const uint32_t pss_n_off = (uint32_t)d.pss[P.k].off.size();
   const uint32_t pss_n_st = (uint32_t)d.pss[P.k].states.size();
-  const uint32_t pss_bytes = (uint32_t)align_up(pss_n_off * 4, 16) + (uint32_t)align_up(pss_n_st * 2, 16);
-  P.lds_bytes = lds_end + 16;
   uint32_t spec_pss_off = 0, spec_pss_states = 0;
-  const uint32_t spec_t1 = n * 16;
-  if (pss_bytes <= 48 * 1024) {
-    spec_pss_off = spec_t1;
-    spec_pss_states = spec_t1 + (uint32_t)align_up(pss_n_off * 4, 16);
-    P.spec_lds_bytes = spec_t1 + pss_bytes + 16;
-  } else {
-    P.spec_lds_bytes = spec_t1 + 16;
+  if (pss_lds_bytes(d, P.k)) {
+    spec_pss_off = lds_end;
+    spec_pss_states = lds_end + (uint32_t)align_up(pss_n_off * 4, 16);
+    lds_end += pss_lds_bytes(d, P.k);
   }
+  P.lds_bytes = lds_end + 16;
   // workspace layout
   const uint64_t nc = P.n_chunks;
   size_t off = 0;
