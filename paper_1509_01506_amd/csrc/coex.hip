@@ -271,18 +271,41 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX
     fixed_total = out_cnt;
   }
   if (valid) {
-    if (!fixed) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)c;
-    else if (a.chunk_cnt) a.chunk_cnt[c] = out_cnt;
+    // the first chunk of every tile goes to the fix-up kernel without a list
+    // entry (its symbols before the converging point are kept for it); the
+    // others only when their join could not be done here
+    if (!fixed && lane > 0) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)c;
+    else if (fixed && a.chunk_cnt) a.chunk_cnt[c] = out_cnt;
+    if (lane == 0 && conv) {
+      uint64_t sy0, sy1, rs;
+      const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+      if ((lo & 63) == 0 && lo + SPEC_WIN <= a.n) front_symbols<ENC>(a, lo, sy0, sy1, rs);
+      else stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
+      uint64_t* f = a.front + 3 * (c / TILE);
+      f[0] = sy0;
+      f[1] = sy1;
+      f[2] = rs;
+    }
     if (fixed) a.conv_t[c] = my_t | FIXED;
     a.end_s[c] = out_e;
     a.tail_cnt[c] = out_cnt;
   }
-  for (int o = 32; o > 0; o >>= 1) fixed_total += __shfl_down(fixed_total, o);
-  if (lane == 0 && fixed_total) atomicAdd(a.total, (unsigned long long)fixed_total);
   if constexpr (HIST) {
+    // per-pattern counts come from the visit histogram
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x)
       if (hist[i]) atomicAdd(a.visits + i, (unsigned long long)hist[i]);
+  } else {
+    // one atomic per block for the joined chunks' total
+    for (int o = 32; o > 0; o >>= 1) fixed_total += __shfl_down(fixed_total, o);
+    uint64_t* red = reinterpret_cast<uint64_t*>(lds + a.lds_red_off);
+    if (lane == 0) red[threadIdx.x >> 6] = fixed_total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+      for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) t += red[w];
+      if (t) atomicAdd(a.total, (unsigned long long)t);
+    }
   }
 }
 
@@ -290,7 +313,12 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX
 // to the chunk end (tables in global memory; this is the rare path).
 template <int ENC, int SHIFT, int STEP>
 __global__ __launch_bounds__(256) void k_nonconv(ScanArgs a) {
-  const Tab tb{reinterpret_cast<const char*>(a.T2), reinterpret_cast<const char*>(a.T1), a.q0s};
+  static_assert(STEP == 1, "one symbol per lookup");
+  extern __shared__ __align__(16) char lds[];
+  if (*a.nc_count == 0u) return;  // the common case: every chunk converged
+  copy_to_lds(lds, a.T1, a.n_states * 16u);
+  __syncthreads();
+  const Tab tb{nullptr, lds, a.q0s};
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   const uint32_t n_nc = *a.nc_count;
@@ -349,11 +377,17 @@ __global__ void k_compose(ScanArgs a) {
 // converged state, and add the chunk's total.
 template <int ENC, int SHIFT, int STEP>
 __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state) {
-  const Tab tb{reinterpret_cast<const char*>(a.T2), reinterpret_cast<const char*>(a.T1), a.q0s};
-  const uint32_t n_fix = *a.fix_count;
+  static_assert(STEP == 1, "the fix-up walks one symbol per lookup");
+  // one-symbol table in LDS: the recounts are chains of dependent lookups
+  extern __shared__ __align__(16) char lds[];
+  copy_to_lds(lds, a.T1, a.n_states * 16u);
+  __syncthreads();
+  const Tab tb{nullptr, lds, a.q0s};
+  const uint64_t n_imp = a.n_tiles;  // the first chunk of every tile
+  const uint64_t n_fix = n_imp + *a.fix_count;
   uint64_t mine_sum = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_fix; i += gridDim.x * blockDim.x) {
-    const uint64_t c = a.fix_list[i];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_fix; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = i < n_imp ? i * TILE : a.fix_list[i - n_imp];
     const uint64_t lo = c * a.chunk;
     const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     SinkGlobal sink{a.wtab, per_state ? a.visits : nullptr};
@@ -365,7 +399,13 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state) {
       if (e != a.true_start[c + 1]) atomicOr(a.err, 2u);
       mine = sink.cnt;
     } else {
-      const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, lo + ct, sink);
+      uint32_t e;
+      if (i < n_imp) {  // symbols kept by the scan kernel
+        const uint64_t* f = a.front + 3 * i;
+        e = run_staged<SHIFT>(tb, s0, f[0], f[1], f[2], ct, lo, sink);
+      } else {
+        e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, lo + ct, sink);
+      }
       if (e != a.conv_s[c]) atomicOr(a.err, 4u);
       mine = (uint64_t)sink.cnt + a.tail_cnt[c];
     }
@@ -644,7 +684,7 @@ uint32_t pss_lds_bytes(const Dfa& d, uint32_t k) {
 uint32_t tail_lds_bytes(uint32_t step, const Dfa& d, uint32_t k) {
   const uint32_t n = d.n_states;
   const uint32_t acc = (uint32_t)align_up(d.n_accepting * 4, 16);
-  return (step == 2 ? n * 64 : 0) + n * 16 + 2 * acc + pss_lds_bytes(d, k) + 16;
+  return (step == 2 ? n * 64 : 0) + n * 16 + 2 * acc + pss_lds_bytes(d, k) + (kScanBlock / 64) * 8 + 16;
 }
 
 template <int ENC, int SHIFT, int STEP, bool HIST>
@@ -765,12 +805,18 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
   }
   if (P.hist) launch_scan<ENC, SHIFT, STEP, true>(P, a, n_cu, st, timed);
   else launch_scan<ENC, SHIFT, STEP, false>(P, a, n_cu, st, timed);
-  constexpr int DSTEP = 1;  // kernels with global tables: one-symbol lookups (the two-symbol walk reads LDS)
-  hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), 0, st, a);
+  constexpr int DSTEP = 1;  // non-converged runs and prefix recounts: one-symbol table staged in LDS
+  const uint32_t nc_lds = a.n_states * 16u + 16u;
+  (void)hipFuncSetAttribute((const void*)k_nonconv<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)nc_lds);
+  hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), nc_lds, st, a);
   const uint32_t cb = (uint32_t)((P.n_chunks + 1 + 255) / 256);
   hipLaunchKernelGGL(k_compose, dim3(cb), dim3(256), 0, st, a);
   const uint32_t fb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P.n_chunks + 255) / 256, n_cu));
-  hipLaunchKernelGGL((k_fixup<ENC, SHIFT, DSTEP>), dim3(fb), dim3(256), 0, st, a, (int)P.hist);
+  const uint32_t t1_lds = a.n_states * 16u + 16u;
+  (void)hipFuncSetAttribute((const void*)k_fixup<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)t1_lds);
+  hipLaunchKernelGGL((k_fixup<ENC, SHIFT, DSTEP>), dim3(fb), dim3(256), t1_lds, st, a, (int)P.hist);
   if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
 }
 
@@ -814,12 +860,14 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   // when it is small
   const uint32_t pss_n_off = (uint32_t)d.pss[P.k].off.size();
   const uint32_t pss_n_st = (uint32_t)d.pss[P.k].states.size();
-  uint32_t spec_pss_off = 0, spec_pss_states = 0;
+  uint32_t spec_pss_off = 0, spec_pss_states = 0, a_red_off_tmp = 0;
   if (pss_lds_bytes(d, P.k)) {
     spec_pss_off = lds_end;
     spec_pss_states = lds_end + (uint32_t)align_up(pss_n_off * 4, 16);
     lds_end += pss_lds_bytes(d, P.k);
   }
+  a_red_off_tmp = lds_end;  // per-wave partial sums of the scan kernel
+  lds_end += (kScanBlock / 64) * 8;
   P.lds_bytes = lds_end + 16;
   // workspace layout
   const uint64_t nc = P.n_chunks;
@@ -830,6 +878,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   size_t o_fxc = take(4), o_fxl = take(nc * 4);
   size_t o_nca = take(nc * P.max_cand * 4), o_nen = take(nc * P.max_cand * 4);
   size_t o_ts = take((nc + 1) * 4), o_vis = take((size_t)d.n_accepting * 8), o_tot = take(8), o_err = take(4);
+  size_t o_front = take((size_t)P.n_tiles * 3 * 8);
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
   rc = workspace(C.dev, stream, off, C.ws, C.wsp);
   if (rc) return rc;
@@ -866,6 +915,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.fix_count = reinterpret_cast<uint32_t*>(w + o_fxc);
   a.fix_list = reinterpret_cast<uint32_t*>(w + o_fxl);
   a.spec_pss_off = spec_pss_off;
+  a.lds_red_off = a_red_off_tmp;
   a.spec_pss_states = spec_pss_states;
   a.pss_n_off = pss_n_off;
   a.pss_n_states = pss_n_st;
@@ -878,6 +928,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.visits = reinterpret_cast<unsigned long long*>(w + o_vis);
   a.total = reinterpret_cast<unsigned long long*>(w + o_tot);
   a.err = reinterpret_cast<uint32_t*>(w + o_err);
+  a.front = reinterpret_cast<uint64_t*>(w + o_front);
   a.chunk_cnt = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_cc) : nullptr;
   C.chunk_off = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_co) : nullptr;
   a.chunk_off = C.chunk_off;

@@ -89,8 +89,10 @@ struct ScanArgs {
   uint32_t* conv_s;           // state there
   uint32_t* end_s;            // state at the chunk end (converged chunks)
   uint32_t* tail_cnt;         // matches in [conv_t, end)
-  uint32_t* fix_count;        // chunks left for the fix-up kernel
+  uint32_t* fix_count;        // chunks left for the fix-up kernel besides the first chunk of every tile
   uint32_t* fix_list;
+  uint64_t* front;            // per tile: the first SPEC_WIN symbols of its first chunk (3 words)
+  uint32_t lds_red_off;       // LDS byte offset of the per-wave partial sums (scan kernel)
   uint32_t spec_pss_off;      // LDS byte offsets of the PSS table in the speculation kernel (0: not staged)
   uint32_t spec_pss_states;
   uint32_t pss_n_off;
