@@ -187,9 +187,10 @@ typedef struct coex_dfa_set coex_dfa_set;
 typedef struct coex_batch coex_batch;
 
 /* Resident automata: their tables packed into LDS groups on the current
-   device (two-symbol rows for automata of at most 1024 states and at most 15
+   device (two-symbol rows for automata of at most 960 states and at most 15
    patterns per state, one-symbol rows for the others; a group holds up to
-   1024 or 4096 states of one kind).  opts may be NULL; opts->width caps the
+   960 or 4096 states of one kind; two-symbol groups also stage their
+   one-symbol rows for the speculation).  opts may be NULL; opts->width caps the
    possible starting states of a chunk (1..64, default 64; a lane runs them in
    batches of 8 registers, merging each batch into the next at its converging
    point) and opts->step forces 1 or 2 symbols per lookup.  The set copies

@@ -44,7 +44,7 @@ namespace batch {
 
 constexpr int kBlock = COEX_SCAN_BLOCK;
 constexpr uint32_t kPad = 0xFFFFFFFFu;      // pair slot without an automaton
-constexpr uint32_t kGroupStates2 = 1024;    // two-symbol rows: 16-bit row offsets of 64 B rows
+constexpr uint32_t kGroupStates2 = 960;     // two-symbol rows (64 B, 16-bit row offsets) + one-symbol rows in LDS
 constexpr uint32_t kGroupStates1 = 4096;    // one-symbol rows: 16-bit row offsets of 16 B rows
 
 struct SeqD {
@@ -74,10 +74,13 @@ struct GroupD {
   uint64_t lane0;     // first lane of the launch
   uint64_t n_lanes;   // units * D
   uint64_t unit0;     // first unit
+  uint64_t n_units;
   uint32_t task0;     // first block task
   uint32_t D;         // pair slots per entry
   uint32_t tab_bytes; // LDS image bytes
   uint32_t step;      // symbols per LDS lookup (2: 64 B rows, state = row offset; 1: 16 B rows)
+  uint32_t t1_lds_off;  // two-symbol groups: LDS offset of the one-symbol rows staged after the image
+  uint32_t t1_bytes;    // 0 for one-symbol groups (their image is the one-symbol rows)
   const uint32_t* tab;   // LDS image
   const uint32_t* t1;    // one-symbol rows in global memory, same register values
   const uint32_t* wtab;  // weight (patterns) per accepting index of the group
@@ -136,6 +139,83 @@ __global__ void k_binit(Args A) {
 
 constexpr int W = 8;  // candidate registers per lane
 
+// Lanes of a group come in spans of 64 * D: in a span, the 64 lanes of slot
+// j hold 64 consecutive units, so one wave walks one automaton's table
+// (lanes often share rows) while the D waves of a span read the same
+// sequence bytes, mostly from cache.
+__host__ __device__ __forceinline__ uint64_t lane_of(uint64_t u, uint32_t j, uint32_t D) {
+  return (u / 64) * 64 * D + (uint64_t)j * 64 + (u % 64);
+}
+__device__ __forceinline__ void unit_of(uint64_t L, uint32_t D, uint64_t& u, uint32_t& j) {
+  const uint64_t span = 64ull * D;
+  const uint64_t r = L % span;
+  j = (uint32_t)(r / 64);
+  u = (L / span) * 64 + (r % 64);
+}
+
+// Byte sequences are converted once per run to 2-bit codes and an N mask
+// (the encoding of the genome scan): every automaton of a chunk then reads
+// 0.375 B/base with no per-lane decoding.
+struct ConvArgs {
+  const SeqD* src;        // byte sequences
+  const SeqD* dst;        // their 2-bit copies (codes, mask, n)
+  const uint64_t* prefix; // n_seq + 1: first 64-base group of each sequence
+  uint32_t n_seq;
+  uint64_t total;         // 64-base groups in all
+};
+
+__global__ __launch_bounds__(256) void k_bconvert(ConvArgs C) {
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < C.total;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = C.n_seq;  // last sequence whose first group is <= g
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (C.prefix[mid] <= g) lo = mid;
+      else hi = mid;
+    }
+    const SeqD in = C.src[lo], out = C.dst[lo];
+    const uint64_t base = (g - C.prefix[lo]) * 64;
+    uint32_t x[16];
+    if (base + 64 <= in.n) {
+      const uint4* src = reinterpret_cast<const uint4*>(in.bases + base);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint4 v = src[i];
+        x[4 * i] = v.x; x[4 * i + 1] = v.y; x[4 * i + 2] = v.z; x[4 * i + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = 0x41414141u;  // past the end: never read by the scan
+      for (uint64_t j = base; j < in.n; ++j) {
+        const uint32_t k = (uint32_t)(j - base);
+        x[k >> 2] = (x[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | ((uint32_t)in.bases[j] << (8 * (k & 3)));
+      }
+    }
+    uint32_t codes[4];
+    uint64_t rst = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t cw = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t v = x[4 * w + i];
+        const uint32_t t = (v >> 1) & 0x03030303u;                      // table column A,C,T,G
+        const uint32_t expect = __builtin_amdgcn_perm(0u, 0x47544341u, t);
+        const uint32_t bad = (v & 0xDFDFDFDFu) ^ expect;                 // nonzero byte: not ACGTacgt
+        const uint32_t code = t ^ ((t >> 1) & 0x01010101u);              // A,C,G,T = 0..3
+        const uint32_t u = code | (code >> 6);
+        cw |= ((u & 0xFu) | ((u >> 12) & 0xF0u)) << (8 * i);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          rst |= (uint64_t)(((bad >> (8 * j)) & 0xFFu) != 0u) << (16 * w + 4 * i + j);
+      }
+      codes[w] = cw;
+    }
+    *reinterpret_cast<uint4*>(const_cast<uint8_t*>(out.bases) + base / 4) = make_uint4(codes[0], codes[1], codes[2], codes[3]);
+    *reinterpret_cast<uint2*>(const_cast<uint8_t*>(out.nmask) + base / 8) = make_uint2((uint32_t)rst, (uint32_t)(rst >> 32));
+  }
+}
+
 // One symbol for the active candidate slots; returns whether all slots
 // below n now hold the same state.
 template <int ENC, int SHIFT>
@@ -172,9 +252,11 @@ __device__ __forceinline__ bool step_slots(const Tab& tg, const uint32_t* wtab, 
 // agreed at its converging point (counts after a common state are common).
 template <int ENC, int SHIFT, int STEP>
 __device__ __forceinline__ void lane_scan(const Args& A, const GroupD& G, const char* lds, uint64_t gl, uint64_t L) {
-  const uint32_t D = G.D;
-  const UnitD un = A.units[G.unit0 + L / D];
-  const uint32_t j = (uint32_t)(L % D);
+  uint64_t ul;
+  uint32_t j;
+  unit_of(L, G.D, ul, j);
+  if (ul >= G.n_units) return;  // padding of the last span
+  const UnitD un = A.units[G.unit0 + ul];
   const EntryD en = A.entries[un.entry];
   const uint32_t slot = en.slot0 + j;
   const uint32_t d = A.slot_dfa[slot];
@@ -188,7 +270,9 @@ __device__ __forceinline__ void lane_scan(const Args& A, const GroupD& G, const 
   sa.k = df.k;
   const uint64_t lo = (uint64_t)un.chunk * A.chunk;
   const uint64_t hi = (un.chunk + 1 == en.n_chunks) ? sq.n : lo + A.chunk;
-  const Tab tg{nullptr, reinterpret_cast<const char*>(G.t1), df.q0s};
+  // one-symbol rows in LDS (after the two-symbol image, or the image itself)
+  const char* t1l = STEP == 2 ? lds + G.t1_lds_off : lds;
+  const Tab tg{nullptr, t1l, df.q0s};
   uint32_t m, cbase, exact;
   bool is_exact;
   chunk_header<ENC, SHIFT>(sa, tg, df.pss_off, lo, m, cbase, exact, is_exact);
@@ -263,7 +347,7 @@ __device__ __forceinline__ void lane_scan(const Args& A, const GroupD& G, const 
     }
     return;
   }
-  const Tab tb{lds, STEP == 2 ? reinterpret_cast<const char*>(G.t1) : lds, df.q0s};
+  const Tab tb{lds, t1l, df.q0s};
   SinkTotal sink{G.wtab};
   const uint32_t e_end = scan_range<ENC, SHIFT, STEP>(sa, tb, rep, T, hi, sink);
   A.rec_end[gl] = e_end;
@@ -298,13 +382,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(COEX_TAI
     // group fields are uniform over the block: keep them in scalar registers
     G.D = __builtin_amdgcn_readfirstlane(G.D);
     G.step = __builtin_amdgcn_readfirstlane(G.step);
+    G.t1_lds_off = __builtin_amdgcn_readfirstlane(G.t1_lds_off);
+    G.t1_bytes = __builtin_amdgcn_readfirstlane(G.t1_bytes);
     G.unit0 = uniform64(G.unit0);
     G.lane0 = uniform64(G.lane0);
     G.n_lanes = uniform64(G.n_lanes);
+    G.n_units = uniform64(G.n_units);
     G.t1 = reinterpret_cast<const uint32_t*>(uniform64(reinterpret_cast<uint64_t>(G.t1)));
     G.wtab = reinterpret_cast<const uint32_t*>(uniform64(reinterpret_cast<uint64_t>(G.wtab)));
     if ((int)g != staged) {
       stage(lds, G.tab, G.tab_bytes);
+      if (G.t1_bytes) stage(lds + G.t1_lds_off, G.t1, G.t1_bytes);
       staged = (int)g;
     }
     __syncthreads();
@@ -333,7 +421,7 @@ __global__ void k_bcompose(Args A) {
   uint32_t q = df.q0s;
   unsigned long long add = 0;
   for (uint32_t c = 0; c < en.n_chunks; ++c) {
-    const uint64_t gl = G.lane0 + (uint64_t)(en.unit0 - G.unit0 + c) * G.D + j;
+    const uint64_t gl = G.lane0 + lane_of((uint64_t)(en.unit0 - G.unit0 + c), j, G.D);
     if (A.rec_t[gl] == NONCONV) {
       const uint32_t m = A.nc_m[gl];
       uint32_t i = 0;
@@ -365,9 +453,12 @@ __global__ void k_bfix(Args A) {
     while (g + 1 < A.n_groups && A.groups[g + 1].lane0 <= gl) ++g;
     const GroupD G = A.groups[g];
     const uint64_t L = gl - G.lane0;
-    const UnitD un = A.units[G.unit0 + L / G.D];
+    uint64_t ul;
+    uint32_t j;
+    unit_of(L, G.D, ul, j);
+    const UnitD un = A.units[G.unit0 + ul];
     const EntryD en = A.entries[un.entry];
-    const uint32_t slot = en.slot0 + (uint32_t)(L % G.D);
+    const uint32_t slot = en.slot0 + j;
     const DfaD df = A.dfas[A.slot_dfa[slot]];
     const SeqD sq = A.seqs[en.seq];
     ScanArgs sa{};
@@ -376,7 +467,7 @@ __global__ void k_bfix(Args A) {
     sa.n = sq.n;
     const char* t1 = reinterpret_cast<const char*>(G.t1);
     const uint32_t sh = G.step == 2 ? 2u : 0u;  // state register -> one-symbol row offset
-    const uint32_t prev = gl - G.D;
+    const uint64_t prev = G.lane0 + lane_of(ul - 1, j, G.D);  // the same entry's previous chunk
     uint32_t q = A.rec_t[prev] == NONCONV ? A.rec_ts[gl] : A.rec_end[prev];
     const uint64_t lo = (uint64_t)un.chunk * A.chunk;
     const uint32_t t = A.rec_t[gl];
@@ -495,6 +586,11 @@ struct coex_batch {
   uint32_t n_tasks = 0, n_slots = 0, max_D = 0;
   coex::batch::Args args{};
   coex::batch::DevBuf desc, recs;
+  // byte input converted to 2-bit codes + N mask once per run
+  bool convert = false;
+  int scan_enc = 0;
+  coex::batch::ConvArgs cargs{};
+  coex::batch::DevBuf conv;
   // graph replay
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -659,6 +755,8 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
       G = GroupD{};
       G.tab_bytes = S->groups[g].tab_bytes;
       G.step = S->groups[g].step;
+      G.t1_lds_off = G.step == 2 ? G.tab_bytes : 0u;
+      G.t1_bytes = G.step == 2 ? S->groups[g].n_states * 16u : 0u;
       G.tab = reinterpret_cast<const uint32_t*>(S->buf.p + S->groups[g].off_tab[e]);
       G.t1 = reinterpret_cast<const uint32_t*>(S->buf.p + S->groups[g].off_t1[e]);
       G.wtab = reinterpret_cast<const uint32_t*>(S->buf.p + S->groups[g].off_w);
@@ -683,6 +781,9 @@ void launch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs_o
                               (int)B.lds_bytes);
     return;
   }
+  if (B.convert && B.cargs.total)
+    hipLaunchKernelGGL(k_bconvert, dim3((uint32_t)std::min<uint64_t>((B.cargs.total + 255) / 256, 8192)), dim3(256), 0,
+                       st, B.cargs);
   hipLaunchKernelGGL(k_binit, dim3(std::max<uint32_t>(1, std::min<uint32_t>((B.n_pairs + 255) / 256, 1024))),
                      dim3(256), 0, st, A);
   if (B.n_tasks) {
@@ -698,7 +799,7 @@ void launch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs_o
 // attrs_only: set the scan kernel's LDS limit (outside any graph capture).
 void dispatch(Batch& B, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool attrs_only = false) {
   const Set& S = *B.set;
-  const bool by = B.enc == 0;
+  const bool by = B.scan_enc == 0;
   const bool a = attrs_only;
   (void)S;
   by ? launch<ENC_BYTE>(B, st, e0, e1, a) : launch<ENC_2BIT>(B, st, e0, e1, a);
@@ -730,7 +831,9 @@ uint64_t default_chunk(const Batch& B, uint64_t lane_bases) {
 // Descriptors and records for the current chunk length.
 int layout(Batch& B) {
   const Set& S = *B.set;
-  const int e = B.enc;
+  B.convert = B.enc == 0;
+  B.scan_enc = 1;
+  const int e = B.scan_enc;
   const uint64_t C = B.chunk;
   const size_t ng = S.groups.size();
   // entries: (group, sequence) with the pair slots of that group
@@ -771,7 +874,8 @@ int layout(Batch& B) {
       for (uint64_t c = 0; c < K; ++c) units.push_back(UnitD{eid, (uint32_t)c});
       entries.push_back(en);
     }
-    G.n_lanes = (units.size() - G.unit0) * (uint64_t)G.D;
+    G.n_units = units.size() - G.unit0;
+    G.n_lanes = (G.n_units + 63) / 64 * 64 * (uint64_t)G.D;
     lane0 += G.n_lanes;
     task0 += (uint32_t)((G.n_lanes + kBlock - 1) / kBlock);
     B.max_D = std::max(B.max_D, G.D);
@@ -784,8 +888,30 @@ int layout(Batch& B) {
   // chunks may fail to converge only when an automaton's synchronising depth
   // (plus its lookback) reaches the chunk length
   B.needs_nc = S.may_not_converge_below || S.max_sync >= C;
+  // 2-bit copies of byte sequences: codes then mask per sequence, 16-byte aligned
+  std::vector<SeqD> scan_seqs = B.seqs;
+  std::vector<uint64_t> prefix(B.seqs.size() + 1, 0);
+  if (B.convert) {
+    size_t off = 0;
+    std::vector<size_t> co(B.seqs.size()), mo(B.seqs.size());
+    for (size_t i = 0; i < B.seqs.size(); ++i) {
+      const uint64_t groups = (B.seqs[i].n + 63) / 64;
+      prefix[i + 1] = prefix[i] + groups;
+      co[i] = off;
+      off = align_up(off + groups * 16, 256);
+      mo[i] = off;
+      off = align_up(off + groups * 8, 256);
+    }
+    int rc0 = B.conv.reserve(std::max<size_t>(off, 256), B.device);
+    if (rc0) return rc0;
+    for (size_t i = 0; i < B.seqs.size(); ++i)
+      scan_seqs[i] = SeqD{reinterpret_cast<const uint8_t*>(B.conv.p + co[i]),
+                          reinterpret_cast<const uint8_t*>(B.conv.p + mo[i]), B.seqs[i].n};
+  }
   Image img;
-  const size_t o_seq = img.add(B.seqs.data(), B.seqs.size() * sizeof(SeqD));
+  const size_t o_seq = img.add(scan_seqs.data(), scan_seqs.size() * sizeof(SeqD));
+  const size_t o_src = img.add(B.seqs.data(), B.seqs.size() * sizeof(SeqD));
+  const size_t o_pre = img.add(prefix.data(), prefix.size() * 8);
   const size_t o_dfa = img.add(S.dfa_dev[e].data(), S.dfa_dev[e].size() * sizeof(DfaD));
   const size_t o_ent = img.add(entries.data(), entries.size() * sizeof(EntryD));
   const size_t o_unit = img.add(units.data(), units.size() * sizeof(UnitD));
@@ -817,6 +943,8 @@ int layout(Batch& B) {
   char* dp = B.desc.p;
   char* rp = B.recs.p;
   A.seqs = reinterpret_cast<const SeqD*>(dp + o_seq);
+  B.cargs = ConvArgs{reinterpret_cast<const SeqD*>(dp + o_src), reinterpret_cast<const SeqD*>(dp + o_seq),
+                     reinterpret_cast<const uint64_t*>(dp + o_pre), (uint32_t)B.seqs.size(), prefix.back()};
   A.dfas = reinterpret_cast<const DfaD*>(dp + o_dfa);
   A.entries = reinterpret_cast<const EntryD*>(dp + o_ent);
   A.units = reinterpret_cast<const UnitD*>(dp + o_unit);
@@ -828,7 +956,7 @@ int layout(Batch& B) {
   A.n_tasks = B.n_tasks;
   A.n_slots = B.n_slots;
   uint32_t tab_max = 0;
-  for (auto& G : S.groups) tab_max = std::max(tab_max, G.tab_bytes);
+  for (auto& G : S.groups) tab_max = std::max(tab_max, G.tab_bytes + (G.step == 2 ? G.n_states * 16u : 0u));
   A.bcast_off = tab_max;
   B.lds_bytes = tab_max + 16;
   A.chunk = C;
@@ -850,7 +978,7 @@ int layout(Batch& B) {
     A.nc_end = reinterpret_cast<uint32_t*>(rp + r_ne);
     A.nc_cnt = reinterpret_cast<uint32_t*>(rp + r_nc);
   }
-  const uint32_t per_cu = blocks_per_cu(S, e, B.lds_bytes);
+  const uint32_t per_cu = blocks_per_cu(S, B.scan_enc, B.lds_bytes);
   B.blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)B.n_cu * per_cu, B.n_tasks));
   // a new layout invalidates a captured graph
   if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
