@@ -376,7 +376,7 @@ __global__ void k_compose(ScanArgs a) {
 // (the whole chunk if it did not converge), check the run lands on the
 // converged state, and add the chunk's total.
 template <int ENC, int SHIFT, int STEP>
-__global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state) {
+__global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int direct) {
   static_assert(STEP == 1, "the fix-up walks one symbol per lookup");
   // one-symbol table in LDS: the recounts are chains of dependent lookups
   extern __shared__ __align__(16) char lds[];
@@ -391,10 +391,15 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state) {
     const uint64_t lo = c * a.chunk;
     const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     SinkGlobal sink{a.wtab, per_state ? a.visits : nullptr};
-    const uint32_t s0 = a.true_start[c];
+    // direct: every chunk converged (no join kernels ran), so the true first
+    // state is the predecessor's last state
+    const uint32_t s0 = direct ? (c == 0 ? a.q0s : a.end_s[c - 1]) : a.true_start[c];
     uint64_t mine;
     const uint32_t ct = a.conv_t[c];
-    if (ct == NONCONV) {
+    if (direct && ct == NONCONV) {
+      atomicOr(a.err, 128u);
+      mine = 0;
+    } else if (ct == NONCONV) {
       const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
       if (e != a.true_start[c + 1]) atomicOr(a.err, 2u);
       mine = sink.cnt;
@@ -667,6 +672,7 @@ int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) 
 
 struct Plan {
   uint32_t shift, step, k, group, max_cand, blocks, lds_bytes;
+  bool all_conv;  // every chunk's candidates must agree inside the window (synchronising depth)
   uint64_t chunk, n_chunks, n_tiles;
   bool hist;
   int enc;
@@ -767,6 +773,15 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
   }
   P.n_chunks = n == 0 ? 0 : (n + P.chunk - 1) / P.chunk;
   P.n_tiles = (P.n_chunks + TILE - 1) / TILE;
+  // after d symbols any two runs agree (d = synchronising depth), so a chunk
+  // whose window holds d symbols converges; chunk 0 starts exactly
+  {
+    const uint64_t last_len = P.n_chunks ? n - (P.n_chunks - 1) * P.chunk : 0;
+    const uint64_t shortest = P.n_chunks > 1 ? std::min<uint64_t>(P.chunk, last_len) : (uint64_t)SPEC_WIN;
+    // (a chunk with more candidates than lanes in its group is not speculated)
+    P.all_conv = d.sync_depth != kNoSync && d.sync_depth <= std::min<uint64_t>(SPEC_WIN, shortest) &&
+                 P.max_cand <= P.group;
+  }
   return COEX_OK;
 }
 
@@ -806,17 +821,23 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
   if (P.hist) launch_scan<ENC, SHIFT, STEP, true>(P, a, n_cu, st, timed);
   else launch_scan<ENC, SHIFT, STEP, false>(P, a, n_cu, st, timed);
   constexpr int DSTEP = 1;  // non-converged runs and prefix recounts: one-symbol table staged in LDS
-  const uint32_t nc_lds = a.n_states * 16u + 16u;
-  (void)hipFuncSetAttribute((const void*)k_nonconv<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)nc_lds);
-  hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), nc_lds, st, a);
-  const uint32_t cb = (uint32_t)((P.n_chunks + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_compose, dim3(cb), dim3(256), 0, st, a);
+  // counts of an automaton that synchronises inside every chunk's window need
+  // neither non-converged maps nor the true first state of every chunk (the
+  // fix-up reads its predecessor's last state); positions and records do
+  const bool direct = emit_counts && P.all_conv;
+  if (!direct) {
+    const uint32_t nc_lds = a.n_states * 16u + 16u;
+    (void)hipFuncSetAttribute((const void*)k_nonconv<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)nc_lds);
+    hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), nc_lds, st, a);
+    const uint32_t cb = (uint32_t)((P.n_chunks + 1 + 255) / 256);
+    hipLaunchKernelGGL(k_compose, dim3(cb), dim3(256), 0, st, a);
+  }
   const uint32_t fb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P.n_chunks + 255) / 256, n_cu));
   const uint32_t t1_lds = a.n_states * 16u + 16u;
   (void)hipFuncSetAttribute((const void*)k_fixup<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)t1_lds);
-  hipLaunchKernelGGL((k_fixup<ENC, SHIFT, DSTEP>), dim3(fb), dim3(256), t1_lds, st, a, (int)P.hist);
+  hipLaunchKernelGGL((k_fixup<ENC, SHIFT, DSTEP>), dim3(fb), dim3(256), t1_lds, st, a, (int)P.hist, (int)direct);
   if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
 }
 
