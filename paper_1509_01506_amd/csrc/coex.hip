@@ -15,8 +15,9 @@
 //                predecessor's last state (constant maps absorb the chain);
 //   k_fixup      recounts [chunk start, converging point) from the true first
 //                state and checks it reaches the converged state (count
-//                fix-up of Algorithm 1 in an equivalent form);
-//   k_finalize   visits per final state -> per-pattern counts.
+//                fix-up of Algorithm 1 in an equivalent form).
+// Per-pattern counts are added to the caller's buffer as they are found
+// (visits of each final state, spread over the patterns it ends).
 // Positions add an exclusive scan of per-chunk counts and a second pass per
 // chunk from its true first state.
 #include <hip/hip_runtime.h>
@@ -56,7 +57,6 @@ __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
     *a.err = 0;
     *a.total = 0;
   }
-  for (uint32_t i = t; i < a.n_acc; i += gridDim.x * blockDim.x) a.visits[i] = 0;
   if (counts)
     for (uint32_t i = t; i < n_counts; i += gridDim.x * blockDim.x) counts[i] = 0;
 }
@@ -291,10 +291,13 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX
     a.tail_cnt[c] = out_cnt;
   }
   if constexpr (HIST) {
-    // per-pattern counts come from the visit histogram
+    // per-pattern counts: each final state's visits, added to the patterns it ends
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x)
-      if (hist[i]) atomicAdd(a.visits + i, (unsigned long long)hist[i]);
+    if (a.pat_counts)
+      for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x)
+        if (hist[i])
+          for (uint32_t j = a.acc_out_off[i]; j < a.acc_out_off[i + 1]; ++j)
+            atomicAdd(a.pat_counts + a.acc_out_ids[j], (unsigned long long)hist[i]);
   } else {
     // one atomic per block for the joined chunks' total
     for (int o = 32; o > 0; o >>= 1) fixed_total += __shfl_down(fixed_total, o);
@@ -335,7 +338,7 @@ __global__ __launch_bounds__(256) void k_nonconv(ScanArgs a) {
       const bool live = i < m;
       uint32_t s = is_exact ? exact : ((uint32_t)a.pss_states[cbase + (live ? i : 0)] << SHIFT);
       const uint32_t s0 = s;
-      SinkGlobal none{a.wtab, nullptr};
+      SinkGlobal none{a.wtab, nullptr, nullptr, nullptr};
       s = scan_range<ENC, SHIFT, STEP>(a, tb, s, lo, hi, none);
       if (live) {
         a.nc_cand[(uint64_t)slot * a.max_cand + i] = s0;
@@ -380,17 +383,18 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
   static_assert(STEP == 1, "the fix-up walks one symbol per lookup");
   // one-symbol table in LDS: the recounts are chains of dependent lookups
   extern __shared__ __align__(16) char lds[];
+  const uint64_t n_imp = a.n_tiles;  // the first chunk of every tile
+  const uint64_t n_fix = n_imp + *a.fix_count;
+  if ((uint64_t)blockIdx.x * blockDim.x >= n_fix) return;  // no item for this block
   copy_to_lds(lds, a.T1, a.n_states * 16u);
   __syncthreads();
   const Tab tb{nullptr, lds, a.q0s};
-  const uint64_t n_imp = a.n_tiles;  // the first chunk of every tile
-  const uint64_t n_fix = n_imp + *a.fix_count;
   uint64_t mine_sum = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_fix; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t c = i < n_imp ? i * TILE : a.fix_list[i - n_imp];
     const uint64_t lo = c * a.chunk;
     const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-    SinkGlobal sink{a.wtab, per_state ? a.visits : nullptr};
+    SinkGlobal sink{a.wtab, a.acc_out_off, a.acc_out_ids, per_state ? a.pat_counts : nullptr};
     // direct: every chunk converged (no join kernels ran), so the true first
     // state is the predecessor's last state
     const uint32_t s0 = direct ? (c == 0 ? a.q0s : a.end_s[c - 1]) : a.true_start[c];
@@ -419,23 +423,6 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
   }
   for (int o = 32; o > 0; o >>= 1) mine_sum += __shfl_down(mine_sum, o);
   if ((threadIdx.x & 63) == 0 && mine_sum) atomicAdd(a.total, (unsigned long long)mine_sum);
-}
-
-// Per-pattern counts: totals for a one-pattern automaton, else visits of each
-// final state spread over the patterns it ends.
-__global__ void k_finalize(ScanArgs a, uint64_t* counts, int per_state) {
-  if (!per_state) {
-    if (threadIdx.x == 0 && a.n_patterns > 0) counts[0] = *a.total;
-    return;
-  }
-  for (uint32_t p = threadIdx.x; p < a.n_patterns; p += blockDim.x) counts[p] = 0;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x) {
-    const unsigned long long v = a.visits[i];
-    if (!v) continue;
-    for (uint32_t j = a.acc_out_off[i]; j < a.acc_out_off[i + 1]; ++j)
-      atomicAdd(reinterpret_cast<unsigned long long*>(counts + a.acc_out_ids[j]), v);
-  }
 }
 
 // Exclusive prefix of per-chunk counts (one block; each thread a contiguous
@@ -813,11 +800,12 @@ void launch_scan(const Plan& P, const ScanArgs& a, int n_cu, hipStream_t st, Wor
 template <int ENC, int SHIFT, int STEP>
 void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint64_t* counts, bool emit_counts,
                      Workspace* timed) {
+  // counts go straight to the caller's buffer (zeroed here): per pattern from
+  // the visit histograms, or the total of a one-pattern automaton
+  a.pat_counts = emit_counts && P.hist ? reinterpret_cast<unsigned long long*>(counts) : nullptr;
+  if (emit_counts && !P.hist && a.n_patterns > 0) a.total = reinterpret_cast<unsigned long long*>(counts);
   hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, a, counts, emit_counts ? a.n_patterns : 0u);
-  if (P.n_chunks == 0) {
-    if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
-    return;
-  }
+  if (P.n_chunks == 0) return;
   if (P.hist) launch_scan<ENC, SHIFT, STEP, true>(P, a, n_cu, st, timed);
   else launch_scan<ENC, SHIFT, STEP, false>(P, a, n_cu, st, timed);
   constexpr int DSTEP = 1;  // non-converged runs and prefix recounts: one-symbol table staged in LDS
@@ -838,7 +826,6 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
   (void)hipFuncSetAttribute((const void*)k_fixup<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)t1_lds);
   hipLaunchKernelGGL((k_fixup<ENC, SHIFT, DSTEP>), dim3(fb), dim3(256), t1_lds, st, a, (int)P.hist, (int)direct);
-  if (emit_counts) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, counts, (int)P.hist);
 }
 
 // Everything a scan call shares: validation, upload, plan, workspace, args.
@@ -898,7 +885,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   size_t o_ncc = take(4), o_nch = take(nc * 4), o_nsl = take(nc * 4), o_nm = take(nc * 4);
   size_t o_fxc = take(4), o_fxl = take(nc * 4);
   size_t o_nca = take(nc * P.max_cand * 4), o_nen = take(nc * P.max_cand * 4);
-  size_t o_ts = take((nc + 1) * 4), o_vis = take((size_t)d.n_accepting * 8), o_tot = take(8), o_err = take(4);
+  size_t o_ts = take((nc + 1) * 4), o_tot = take(8), o_err = take(4);
   size_t o_front = take((size_t)P.n_tiles * 3 * 8);
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
   rc = workspace(C.dev, stream, off, C.ws, C.wsp);
@@ -946,7 +933,6 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.nc_cand = reinterpret_cast<uint32_t*>(w + o_nca);
   a.nc_end = reinterpret_cast<uint32_t*>(w + o_nen);
   a.true_start = reinterpret_cast<uint32_t*>(w + o_ts);
-  a.visits = reinterpret_cast<unsigned long long*>(w + o_vis);
   a.total = reinterpret_cast<unsigned long long*>(w + o_tot);
   a.err = reinterpret_cast<uint32_t*>(w + o_err);
   a.front = reinterpret_cast<uint64_t*>(w + o_front);

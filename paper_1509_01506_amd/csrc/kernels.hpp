@@ -104,7 +104,7 @@ struct ScanArgs {
   uint32_t* nc_cand;          // slot * max_cand + i -> candidate state
   uint32_t* nc_end;           // slot * max_cand + i -> end state from that candidate
   uint32_t* true_start;       // n_chunks + 1
-  unsigned long long* visits; // per accepting index
+  unsigned long long* pat_counts;  // per pattern (the caller's counts), or NULL
   unsigned long long* total;  // weighted total
   uint64_t* chunk_cnt;        // per chunk total (find / records)
   uint32_t* err;              // device consistency flag
@@ -216,15 +216,18 @@ struct SinkHist {       // per accepting state visits in an LDS histogram
   }
 };
 
-struct SinkGlobal {     // weighted count, and visits straight to global memory
+struct SinkGlobal {     // weighted count, and per-pattern counts straight to global memory
   static constexpr bool kReplay = true;
   const uint32_t* w;
-  unsigned long long* visits;  // NULL: count only
+  const uint32_t* out_off;     // per accepting index: its pattern ids
+  const uint32_t* out_ids;
+  unsigned long long* pat;     // NULL: count only
   uint32_t cnt = 0;
   __device__ void word(uint32_t) {}
   __device__ void hit(uint64_t, uint32_t a) {
     cnt += w[a];
-    if (visits) atomicAdd(visits + a, 1ull);
+    if (pat)
+      for (uint32_t j = out_off[a]; j < out_off[a + 1]; ++j) atomicAdd(pat + out_ids[j], 1ull);
   }
 };
 
