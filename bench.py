@@ -236,7 +236,7 @@ def bench_serving(args, w):
     from synth import configs
     pool_np = configs.serving_pool()
     pool = torch.from_numpy(pool_np).pin_memory()
-    srv = coex.Server(w["dfas"], hbm_budget=8 << 30)
+    srv = coex.Server(w["dfas"], hbm_budget=8 << 30, copy_piece=args.copy_piece_mib << 20)
 
     def run(arrivals, sizes, ids, offs):
         tickets = [None] * len(sizes)
@@ -338,6 +338,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--clock-warmup-s", type=float, default=0.5,
                     help="untimed steps for this many seconds before the warm-up steps (sustained clocks)")
+    ap.add_argument("--copy-piece-mib", type=int, default=0,
+                    help="serving: bytes per host-to-device copy piece in MiB (0 = the library's default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (scale for rocprofv3 byte counters)")
     args = ap.parse_args()

@@ -255,8 +255,9 @@ int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_s
    A serving loop over resident automata: requests (one host sequence of
    ASCII bases and one automaton index each) are admitted in arrival order
    into a device arena of `hbm_budget` bytes, copied on a copy stream while
-   earlier batches run, and every admitted request whose copy has finished is
-   launched in the next batch (continuous batching; up to two batches queued
+   earlier batches run (in pieces of `copy_piece` bytes, the request with the
+   fewest bytes left first), and every admitted request whose copy has
+   finished is launched in the next batch (continuous batching; up to two batches queued
    on the compute stream).  A request's count is its pair's count in a batch,
    so it is the same alone or in any mix.  One worker thread per server;
    submit and wait may be called from any thread. */
@@ -269,11 +270,14 @@ typedef struct {
   uint32_t chunk;       /* bases per chunk (0 = chosen per batch) */
   uint32_t width;       /* as coex_dfa_set_create */
   uint32_t flags;       /* reserved, 0 */
+  uint64_t copy_piece;  /* bytes per host-to-device copy piece (0 = 16 MiB); at most three
+                           pieces' worth of bytes is queued on the copy stream at a time */
 } coex_server_opts;
 
 typedef struct {
-  double queue_ms;          /* submit -> admitted (arena space granted, copy queued) */
-  double h2d_ms;            /* device time of the host-to-device copy */
+  double queue_ms;          /* submit -> admitted (arena space granted) */
+  double h2d_ms;            /* device time from the start of the request's first copy piece to the
+                               end of its last (other requests' pieces may run in between) */
   double device_ms;         /* device time of the request's batch (launch to counts copied back) */
   double total_ms;          /* submit -> result available on the host */
   double launch_to_done_ms; /* batch launch -> result available (host clock) */

@@ -71,7 +71,7 @@ _VOID = ("coex_dfa_free", "coex_strerror", "coex_version", "coex_dfa_set_free", 
 
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("width", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("width", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("copy_piece", ctypes.c_uint64)]
 
 
 class _ReqStats(ctypes.Structure):
@@ -454,9 +454,9 @@ class Server:
     automaton index, wait for counts and per-request latencies."""
 
     def __init__(self, dfas: Sequence[Dfa], hbm_budget: int = 0, max_batch: int = 0, chunk: int = 0,
-                 width: int = 0):
+                 width: int = 0, copy_piece: int = 0):
         hs = (ctypes.c_void_p * len(dfas))(*[d.handle.value for d in dfas])
-        o = _ServerOpts(int(hbm_budget), int(max_batch), int(chunk), int(width), 0)
+        o = _ServerOpts(int(hbm_budget), int(max_batch), int(chunk), int(width), 0, int(copy_piece))
         out = ctypes.c_void_p()
         _check(_lib().coex_server_create(ctypes.cast(hs, ctypes.c_void_p), len(dfas), ctypes.byref(o),
                                          ctypes.byref(out)), "server_create")

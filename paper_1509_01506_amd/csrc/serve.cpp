@@ -1,7 +1,11 @@
 // libcoex serving loop: scan requests (a host sequence of ASCII bases and the
 // index of a resident automaton) arrive one at a time; a worker thread
 //   - admits them in arrival order into a device arena bounded by an HBM
-//     budget, copying each on a copy stream as soon as it is admitted;
+//     budget;
+//   - copies admitted requests to the device in pieces on a copy stream, with
+//     at most three pieces' worth of bytes queued at a time, the request with
+//     the fewest bytes left first, so a small request never waits behind the
+//     whole copy of a large one;
 //   - launches every admitted request whose copy has finished as one batch
 //     over the resident automaton set (continuous batching: requests that
 //     arrive while a batch runs join the next one);
@@ -22,6 +26,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "coex.h"
@@ -83,7 +88,8 @@ struct Req {
   uint32_t dfa = 0;
   Clock::time_point t_submit, t_admit, t_launch, t_done;
   size_t off = 0, bytes = 0;
-  hipEvent_t c0 = nullptr, c1 = nullptr;  // around the host-to-device copy
+  uint64_t copied = 0;                    // bytes whose copy has been queued
+  hipEvent_t c0 = nullptr, c1 = nullptr;  // before the first and after the last piece of its copy
   float device_ms = 0.f, h2d_ms = 0.f;
   uint64_t count = 0;
   uint32_t batch_size = 0;
@@ -116,7 +122,13 @@ struct coex_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req*> pending;
-  std::vector<Req*> resident;
+  std::vector<Req*> copying;   // admitted, copy not fully queued
+  std::vector<Req*> resident;  // copy fully queued (launched once it has finished)
+  uint64_t piece = 16ull << 20;  // bytes per copy piece
+  std::deque<std::pair<hipEvent_t, uint64_t>> inflight;  // event after each queued piece, its bytes
+  std::deque<hipEvent_t> spare;
+  uint64_t inflight_bytes = 0;
+  uint64_t inflight_cap = 48ull << 20;  // bytes of queued pieces before the next is queued
   std::map<uint64_t, Req*> reqs;
   Slot slots[2];
   std::thread worker;
@@ -196,25 +208,77 @@ bool admit(coex_server* S) {
     r->off = off;
     r->bytes = need;
     r->t_admit = Clock::now();
-    int st = COEX_OK;
-    if (hipEventCreate(&r->c0) != hipSuccess || hipEventCreate(&r->c1) != hipSuccess) st = COEX_EDEVICE;
-    if (st == COEX_OK && r->n) {
-      if (hipEventRecord(r->c0, S->copy_st) != hipSuccess ||
-          hipMemcpyAsync(S->arena.base + off, r->host, r->n, hipMemcpyHostToDevice, S->copy_st) != hipSuccess)
-        st = COEX_EDEVICE;
-    } else if (st == COEX_OK && hipEventRecord(r->c0, S->copy_st) != hipSuccess) {
-      st = COEX_EDEVICE;
-    }
-    if (st == COEX_OK && hipEventRecord(r->c1, S->copy_st) != hipSuccess) st = COEX_EDEVICE;
     S->pending.pop_front();
-    if (st != COEX_OK) {
+    if (hipEventCreate(&r->c0) != hipSuccess || hipEventCreate(&r->c1) != hipSuccess) {
       S->arena.release(off, need);
-      finish(S, r, st);
+      finish(S, r, COEX_EDEVICE);
       S->cv_done.notify_all();
       continue;
     }
-    S->resident.push_back(r);
+    S->copying.push_back(r);
     S->stats.max_arena_bytes = std::max<uint64_t>(S->stats.max_arena_bytes, S->arena.used);
+    any = true;
+  }
+  return any;
+}
+
+// Queues copy pieces while less than three pieces' worth of bytes is in
+// flight: the next piece of the admitted request with the fewest bytes left
+// (the earliest admitted among equals).  A request whose last piece is
+// queued becomes resident.  Pieces trade copy efficiency (each copy has a
+// fixed cost) for the wait of a small request behind a large one.
+constexpr size_t kMaxInflightPieces = 64;
+
+bool feed(coex_server* S) {
+  bool any = false;
+  while (!S->inflight.empty() && hipEventQuery(S->inflight.front().first) != hipErrorNotReady) {
+    S->spare.push_back(S->inflight.front().first);
+    S->inflight_bytes -= S->inflight.front().second;
+    S->inflight.pop_front();
+  }
+  while (!S->copying.empty() && S->inflight.size() < kMaxInflightPieces && S->inflight_bytes < S->inflight_cap) {
+    size_t best = 0;
+    for (size_t i = 1; i < S->copying.size(); ++i)
+      if (S->copying[i]->n - S->copying[i]->copied < S->copying[best]->n - S->copying[best]->copied) best = i;
+    Req* r = S->copying[best];
+    const uint64_t len = std::min<uint64_t>(r->n - r->copied, S->piece);
+    int st = COEX_OK;
+    if (r->copied == 0 && hipEventRecord(r->c0, S->copy_st) != hipSuccess) st = COEX_EDEVICE;
+    if (st == COEX_OK && len &&
+        hipMemcpyAsync(S->arena.base + r->off + r->copied, static_cast<const char*>(r->host) + r->copied, len,
+                       hipMemcpyHostToDevice, S->copy_st) != hipSuccess)
+      st = COEX_EDEVICE;
+    hipEvent_t ev = nullptr;
+    if (st == COEX_OK) {
+      if (!S->spare.empty()) {
+        ev = S->spare.front();
+        S->spare.pop_front();
+      } else if (hipEventCreate(&ev) != hipSuccess) {
+        ev = nullptr;
+        st = COEX_EDEVICE;
+      }
+    }
+    if (st == COEX_OK && hipEventRecord(ev, S->copy_st) != hipSuccess) st = COEX_EDEVICE;
+    if (ev && st == COEX_OK) {
+      S->inflight.emplace_back(ev, len);
+      S->inflight_bytes += len;
+    } else if (ev) {
+      S->spare.push_back(ev);
+    }
+    r->copied += len;
+    const bool last = r->copied == r->n;
+    if (st == COEX_OK && last && hipEventRecord(r->c1, S->copy_st) != hipSuccess) st = COEX_EDEVICE;
+    if (st != COEX_OK || last) S->copying.erase(S->copying.begin() + (std::ptrdiff_t)best);
+    if (st != COEX_OK) {
+      // queued pieces may still be writing the request's arena range: wait
+      // for the copy stream before the range can be reused
+      (void)hipStreamSynchronize(S->copy_st);
+      S->arena.release(r->off, r->bytes);
+      finish(S, r, st);
+      S->cv_done.notify_all();
+    } else if (last) {
+      S->resident.push_back(r);
+    }
     any = true;
   }
   return any;
@@ -271,8 +335,10 @@ void loop(coex_server* S) {
   for (;;) {
     bool any = retire(S);
     any |= admit(S);
+    any |= feed(S);
     any |= launch(S);
-    const bool idle = S->pending.empty() && S->resident.empty() && !S->slots[0].busy && !S->slots[1].busy;
+    const bool idle = S->pending.empty() && S->copying.empty() && S->resident.empty() && S->inflight.empty() &&
+                      !S->slots[0].busy && !S->slots[1].busy;
     if (S->stop && idle) break;
     if (!any) {
       if (idle) S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
@@ -298,6 +364,8 @@ coex_server::~coex_server() {
     if (r->c1) (void)hipEventDestroy(r->c1);
     delete r;
   }
+  for (auto& e : inflight) (void)hipEventDestroy(e.first);
+  for (hipEvent_t e : spare) (void)hipEventDestroy(e);
   for (Slot& sl : slots) {
     if (sl.batch) coex_batch_free(sl.batch);
     if (sl.counts_dev) (void)hipFree(sl.counts_dev);
@@ -326,6 +394,8 @@ int coex_server_create(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_s
     S->n_dfa = n_dfa;
     const uint64_t budget = (o && o->hbm_budget) ? o->hbm_budget : (4ull << 30);
     if (o && o->max_batch) S->max_batch = o->max_batch;
+    if (o && o->copy_piece) S->piece = o->copy_piece;
+    S->inflight_cap = 3 * S->piece;
     if (hipStreamCreateWithFlags(&S->copy_st, hipStreamNonBlocking) != hipSuccess) return COEX_EDEVICE;
     if (hipStreamCreateWithFlags(&S->comp_st, hipStreamNonBlocking) != hipSuccess) return COEX_EDEVICE;
     if (hipMalloc(&S->arena_buf, budget) != hipSuccess) return COEX_ENOMEM;

@@ -60,7 +60,9 @@ def test_alone_and_in_mix(coex):
     dfas = [coex.Dfa.kmers(k) for k in sets] + [coex.Dfa.regex(r) for r in rxs]
     reqs = _requests(60, 85, 400_000)
     expect = [_oracle(sets, rxs, d, seq) for seq, d in reqs]
-    srv = coex.Server(dfas, hbm_budget=64 << 20)
+    # 64 KiB copy pieces: the larger requests are copied in several pieces,
+    # interleaved with the pieces of smaller ones
+    srv = coex.Server(dfas, hbm_budget=64 << 20, copy_piece=1 << 16)
     # in the mix: everything submitted at once from pinned buffers
     bufs = [torch.from_numpy(seq).pin_memory() if seq.size else torch.empty(0, dtype=torch.uint8)
             for seq, _ in reqs]
