@@ -112,3 +112,23 @@ def test_budget_and_refusal(coex):
     # the server keeps working after a refusal
     assert srv.wait(srv.submit(reqs[0][0], reqs[0][1]))[0] == expect[0]
     srv.close()
+
+
+def test_odd_copy_pieces(coex):
+    # copy pieces of 1000 bytes (not a multiple of any alignment) and an arena
+    # smaller than the sum of the requests: pieces of several requests
+    # interleave, the shortest remaining first, and every count stays exact
+    import torch
+    sets, rxs = _patterns()
+    dfas = [coex.Dfa.kmers(k) for k in sets] + [coex.Dfa.regex(r) for r in rxs]
+    reqs = _requests(40, 87, 60_000)
+    expect = [_oracle(sets, rxs, d, seq) for seq, d in reqs]
+    srv = coex.Server(dfas, hbm_budget=512 << 10, copy_piece=1000)
+    bufs = [torch.from_numpy(seq).pin_memory() if seq.size else torch.empty(0, dtype=torch.uint8)
+            for seq, _ in reqs]
+    tickets = [srv.submit(b, d) for b, (_, d) in zip(bufs, reqs)]
+    got = [srv.wait(t) for t in tickets]
+    say("odd pieces stats", srv.stats())
+    assert [g[0] for g in got] == expect
+    assert srv.stats()["max_arena_bytes"] <= 512 << 10
+    srv.close()
