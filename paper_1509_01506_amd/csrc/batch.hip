@@ -165,14 +165,22 @@ struct ConvArgs {
 };
 
 __global__ __launch_bounds__(256) void k_bconvert(ConvArgs C) {
-  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < C.total;
-       g += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t lo = 0, hi = C.n_seq;  // last sequence whose first group is <= g
+  // each block converts one contiguous run of groups; a thread's groups are
+  // 256 apart, so the index of the sequence holding them only moves forward
+  const uint64_t per_block = (C.total + gridDim.x - 1) / gridDim.x;
+  const uint64_t g0 = (uint64_t)blockIdx.x * per_block;
+  const uint64_t g1 = g0 + per_block < C.total ? g0 + per_block : C.total;
+  uint32_t lo = 0;  // last sequence whose first group is <= g
+  if (g0 + threadIdx.x < g1) {
+    uint32_t hi = C.n_seq;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) / 2;
-      if (C.prefix[mid] <= g) lo = mid;
+      if (C.prefix[mid] <= g0 + threadIdx.x) lo = mid;
       else hi = mid;
     }
+  }
+  for (uint64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+    while (lo + 1 < C.n_seq && C.prefix[lo + 1] <= g) ++lo;
     const SeqD in = C.src[lo], out = C.dst[lo];
     const uint64_t base = (g - C.prefix[lo]) * 64;
     uint32_t x[16];
