@@ -289,7 +289,12 @@ def find(dfa: Dfa, seq: DeviceSeq, capacity: Optional[int] = None, chunk: int = 
     s = seq._c()
     o = _opts(chunk, width, lookback, step)
     n_found = ctypes.c_uint64(0)
-    cap = 0 if capacity is None else int(capacity)
+    if capacity is None:
+        # a first guess that holds most results, so the scan usually runs once
+        # (the second call below reruns it with the exact size)
+        cap = min(int(seq.n) * max(1, dfa.info().max_out), 1 << 20)
+    else:
+        cap = int(capacity)
     pos = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
     pat = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
     rc = _lib().coex_find(dfa.handle, ctypes.byref(s), pos.data_ptr(), pat.data_ptr(), cap, ctypes.byref(n_found),
