@@ -266,3 +266,34 @@ def test_full_genome(coex):
     assert got.tolist() == expect.tolist()
     del s
     torch.cuda.empty_cache()
+
+
+def test_beyond_4g_bases(coex):
+    # 2^32 + 2^24 + 777 bases (byte and 2-bit input): chunk offsets, block
+    # addresses and end positions past 2^32; a pattern planted at the very end
+    import torch
+    n = (1 << 32) + (1 << 24) + 777
+    seq = synth.markov_bytes(91, n, with_n=True)
+    kmers = synth.random_kmers(92, 8, 10)
+    seq[-10:] = np.frombuffer(kmers[3].encode(), dtype=np.uint8)
+    say("beyond 4G: generated", n)
+    ec, epos, epat = oracle.count_kmers(kmers, oracle.byte_seq(seq), positions=True)
+    assert epos[-1] == n - 1 and int((epos >= (1 << 32)).sum()) > 0
+    say("beyond 4G: oracle done", int(ec.sum()))
+    d = coex.Dfa.kmers(kmers)
+    s = dev_bytes(coex, seq)
+    assert gpu_counts(coex, d, s).tolist() == ec.tolist()
+    pos, pat = coex.find(d, s)
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+    assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
+    say("beyond 4G: bytes ok")
+    del s
+    packed, mask = synth.bytes_to_2bit(seq)
+    del seq
+    s2 = coex.to_device(packed, n=n, encoding=coex.ENC_2BIT, nmask=mask)
+    assert gpu_counts(coex, d, s2).tolist() == ec.tolist()
+    pos, _ = coex.find(d, s2)
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+    say("beyond 4G: 2-bit ok")
+    del s2, pos, pat
+    torch.cuda.empty_cache()
