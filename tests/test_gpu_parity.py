@@ -297,3 +297,29 @@ def test_beyond_4g_bases(coex):
     say("beyond 4G: 2-bit ok")
     del s2, pos, pat
     torch.cuda.empty_cache()
+
+
+def test_large_automaton(coex):
+    # 460 random 12-mers: about 3,800 states, past the two-symbol limit (1,024):
+    # one-symbol rows with 16-bit state offsets, lookback up to 8 and more
+    # than 64 possible starting states at short lookbacks
+    kmers = synth.random_kmers(95, 460, 12)
+    d = coex.Dfa.kmers(kmers)
+    assert 1024 < d.info().n_states <= 4096
+    n = 2_000_003
+    seq = synth.markov_bytes(96, n, with_n=True)
+    for i in range(0, 40):  # planted occurrences, some across chunk boundaries
+        at = 4093 + i * 49_999
+        seq[at:at + 12] = np.frombuffer(kmers[i * 11].encode(), dtype=np.uint8)
+    ec, epos, epat = oracle.count_kmers(kmers, oracle.byte_seq(seq), positions=True)
+    s = dev_bytes(coex, seq)
+    s2 = dev_2bit(coex, seq)[0]
+    for chunk in [0, 4096, 100_000]:
+        say("large automaton", d.info().n_states, chunk)
+        assert gpu_counts(coex, d, s, chunk=chunk).tolist() == ec.tolist()
+        assert gpu_counts(coex, d, s2, chunk=chunk).tolist() == ec.tolist()
+    pos, pat = coex.find(d, s)
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+    assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
+    with pytest.raises(coex.CoexError):
+        coex.count(d, s, step=2)  # two symbols per lookup need at most 1,024 states
