@@ -323,3 +323,41 @@ def test_large_automaton(coex):
     assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
     with pytest.raises(coex.CoexError):
         coex.count(d, s, step=2)  # two symbols per lookup need at most 1,024 states
+
+
+def test_streams_and_threads(coex):
+    # four host threads, each with its own stream, count concurrently over
+    # shared automaton handles (device copies made on first use) and their own
+    # workspaces; every result equals the oracle
+    import threading
+    import torch
+    pats = [synth.random_kmers(97, 10, 8), synth.random_kmers(98, 30, 11)]
+    dfas = [coex.Dfa.kmers(k) for k in pats]
+    seqs = [synth.markov_bytes(99 + i, 300_000 + 777 * i, with_n=True) for i in range(4)]
+    expect = [[oracle.count_kmers(k, oracle.byte_seq(sq))[0].tolist() for k in pats] for sq in seqs]
+    devs = [dev_bytes(coex, sq) for sq in seqs]
+    torch.cuda.synchronize()
+    got = {}
+    errors = []
+
+    def worker(t):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for r in range(4):
+                    for j, d in enumerate(dfas):
+                        c = coex.count(d, devs[t], chunk=[0, 4096][r % 2], stream=st, check=True)
+                        got[(t, r, j)] = c.cpu().numpy().view(np.uint64).tolist()
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    say("streams and threads:", len(got), "calls")
+    for (t, r, j), v in got.items():
+        assert v == expect[t][j], (t, r, j)
