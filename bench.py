@@ -418,6 +418,8 @@ def main():
 
     algo_bytes = w["n"] * w["bytes_per_base"]
     achieved = algo_bytes / (k_avg_ms * 1e-3) / 1e9
+    sym = 2 if info.n_states <= 1024 else 1  # the planner's default table for the chunk scan
+    lookups_per_clk = w["n"] / sym / (k_avg_ms * 1e-3) / (256 * 2.4e9)
     traffic = measured_traffic(args.workload)
     res = {
         "metric": "Gbases/s scanned (exact counts)",
@@ -438,7 +440,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_tail", "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(k_avg_ms, 4),
-                     "algorithmic_bytes_per_launch": int(algo_bytes)},
+                     "algorithmic_bytes_per_launch": int(algo_bytes),
+                     "note": "the walk is bound by dependent random LDS reads: %.1f table lookups per clock "
+                             "per CU (%d symbols per lookup, 256 CUs at 2.4 GHz)" % (lookups_per_clk, sym)},
     }
     if not args.no_cpu_baseline:
         cb, exact = cpu_baseline(args.workload, w, gpu_counts)
