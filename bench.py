@@ -37,6 +37,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> dict:
+    """The host CPU the baselines ran on: model (as lscpu names it), logical
+    CPUs of the machine and CPUs this process may use."""
+    model = ""
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "usable_cpus": usable}
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -118,8 +147,8 @@ def cpu_baseline(name: str, w, gpu_counts):
         counts = oracle.count_kmers(w["patterns"], oracle.byte_seq(w["host"][0]))[0]
     dt = time.perf_counter() - t0
     exact = [int(x) for x in counts] == [int(x) for x in gpu_counts]
-    return {"value": round(w["n"] / dt / 1e9, 4), "unit": "Gbases/s", "cores": 1, "kind": "oracle",
-            "sample": "the whole workload (%d bases), one thread, %.1f s" % (w["n"], dt)}, exact
+    return dict({"value": round(w["n"] / dt / 1e9, 4), "unit": "Gbases/s", "cores": 1, "kind": "oracle",
+                 "sample": "the whole workload (%d bases), one thread, %.1f s" % (w["n"], dt)}, **host_cpu()), exact
 
 
 def bench_batched(args, w):
@@ -203,25 +232,31 @@ def bench_batched(args, w):
     }
     if not args.no_cpu_baseline:
         import oracle
-        order = np.argsort(w["lengths"])
-        pick, tot = [], 0
-        for s in order[::-1][40:]:       # mid-sized sequences until about 1.5e8 bases
-            if tot > 150_000_000:
-                break
-            pick.append(int(s))
-            tot += int(w["lengths"][s])
+        host = host_cpu()
+        threads = min(16, host["usable_cpus"])
+        lengths, buf, offs = w["lengths"], w["buf"], w["offs"]
         regs = [oracle.Regex(r) for r in w["rxs"]]
+        nk = len(w["sets"])
+        jobs = sorted(((s, d) for s in range(len(lengths)) for d in range(len(w["dfas"]))),
+                      key=lambda sd: -lengths[sd[0]])
+
+        def one(sd):
+            s, d = sd
+            h = oracle.byte_seq(buf[offs[s]:offs[s] + lengths[s]])
+            return int(oracle.count_kmers(w["sets"][d], h)[0].sum()) if d < nk else int(regs[d - nk].scan(h)[0])
+
         t0 = time.perf_counter()
-        exact = True
-        for s in pick:
-            h = oracle.byte_seq(w["buf"][w["offs"][s]:w["offs"][s] + w["lengths"][s]])
-            exp = [int(oracle.count_kmers(k, h)[0].sum()) for k in w["sets"]] + [int(r.scan(h)[0]) for r in regs]
-            exact &= exp == [int(x) for x in got[s]]
+        vals = oracle.pool_map(one, jobs, threads)
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": round(tot / dt / 1e9, 4), "unit": "Gbases/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d sequences (%d bases) x 16 automata, one thread, %.1f s"
-                                         % (len(pick), tot, dt)}
+        exact = all(v == int(got[s, d]) for (s, d), v in zip(jobs, vals))
+        res["cpu_baseline"] = dict({"value": round(n / dt / 1e9, 4), "unit": "Gbases/s", "cores": threads,
+                                    "kind": "oracle",
+                                    "sample": "all %d pairs (%d sequences, %d bases, x %d automata) on a pool of %d "
+                                              "threads, each pair one sequential scan, %.1f s"
+                                              % (len(jobs), len(lengths), n, len(w["dfas"]), threads, dt)}, **host)
         res["exact"] = bool(exact)
+        res["exact_pairs_checked"] = len(jobs)
+        log("oracle: all %d pairs in %.1f s on %d threads; exact=%s" % (len(jobs), dt, threads, exact))
     print(json.dumps(res), flush=True)
 
 
@@ -291,11 +326,33 @@ def bench_serving(args, w):
             "mean_batch": round(float(bs.mean()), 2)}
         log("load %.1f: %s" % (load, points[str(load)]))
         if load == 0.8:
-            order = np.argsort(sz)
-            for i in list(order[: 40]) + list(order[len(order) // 2: len(order) // 2 + 40]) + list(order[-12:]):
-                sample_check.append((int(offs[i]), int(sz[i]), int(ids[i]), res[i][0]))
+            trace8 = (arr, sz, ids, offs)
+            sample_check = [(int(o), int(n), int(d), r[0]) for o, n, d, r in zip(offs, sz, ids, res)]
     st = srv.stats()
     srv.close()
+    # the plain path on the same 0.8 trace: one request at a time, in arrival
+    # order, each a host-to-device copy and one coex_count on one stream
+    arr, sz, ids, offs = trace8
+    dev_buf = torch.empty(int(max(sz)) + 16, dtype=torch.uint8, device="cuda")
+    pout = torch.empty(max(d.info().n_patterns for d in w["dfas"]), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    lat, plain_counts = [], []
+    t0 = time.perf_counter()
+    for a, n, d, o in zip(arr, sz, ids, offs):
+        dt = a - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        dev_buf[:n].copy_(pool[o:o + n], non_blocking=True)
+        r = coex.count(w["dfas"][d], coex.DeviceSeq(dev_buf, n, coex.ENC_BYTE), out=pout)
+        plain_counts.append(int(r.sum().item()))  # synchronises
+        lat.append((time.perf_counter() - t0 - a) * 1e3)
+    pwall = time.perf_counter() - t0
+    lat = np.array(lat)
+    plain = {"requests": len(sz), "wall_s": round(pwall, 2), "gbases_per_s": round(sum(sz) / pwall / 1e9, 2),
+             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+             "same_counts_as_served": plain_counts == [c[3] for c in sample_check]}
+    log("plain path on the 0.8 trace: %s" % plain)
+    del dev_buf
     p8 = points["0.8"]
     result = {
         "metric": "Gbases/s served and p50/p99 latency (exact counts)",
@@ -308,24 +365,34 @@ def bench_serving(args, w):
                    "parallelism": "single GPU"},
         "latency": points, "server": {"batches": st["n_batches"], "requests": st["n_done"],
                                       "max_arena_bytes": st["max_arena_bytes"]},
+        "plain_same_trace_0.8": plain,
     }
     if not args.no_cpu_baseline:
         import oracle
+        host = host_cpu()
+        threads = min(16, host["usable_cpus"])
         regs = [oracle.Regex(r) for r in w["rxs"]]
         nk = len(w["sets"])
-        t0 = time.perf_counter()
-        exact, bases = True, 0
-        for o, n, d, got in sample_check:
+        jobs = sorted(sample_check, key=lambda x: -x[1])
+
+        def one(job):
+            o, n, d, _ = job
             h = oracle.byte_seq(pool_np[o:o + n])
-            e = int(oracle.count_kmers(w["sets"][d], h)[0].sum()) if d < nk else int(regs[d - nk].scan(h)[0])
-            exact &= e == got
-            bases += n
+            return int(oracle.count_kmers(w["sets"][d], h)[0].sum()) if d < nk else int(regs[d - nk].scan(h)[0])
+
+        t0 = time.perf_counter()
+        vals = oracle.pool_map(one, jobs, threads)
         dt = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": round(bases / dt / 1e9, 4), "unit": "Gbases/s", "cores": 1,
-                                  "kind": "oracle",
-                                  "sample": "%d requests of the 0.8 run (%d bases), one thread, %.1f s"
-                                            % (len(sample_check), bases, dt)}
+        bases = sum(j[1] for j in jobs)
+        exact = all(v == j[3] for v, j in zip(vals, jobs))
+        result["cpu_baseline"] = dict({"value": round(bases / dt / 1e9, 4), "unit": "Gbases/s", "cores": threads,
+                                       "kind": "oracle",
+                                       "sample": "every request of the 0.8 run (%d requests, %d bases) on a pool of "
+                                                 "%d threads, each request one sequential scan, %.1f s"
+                                                 % (len(jobs), bases, threads, dt)}, **host)
         result["exact"] = bool(exact)
+        result["exact_requests_checked"] = len(jobs)
+        log("oracle: %d requests in %.1f s on %d threads; exact=%s" % (len(jobs), dt, threads, exact))
     print(json.dumps(result), flush=True)
 
 

@@ -19,6 +19,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 from typing import Optional
 
@@ -78,6 +79,27 @@ def _load():
 
 def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data
+
+
+def host_threads() -> int:
+    """Host cores this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def pool_map(fn, items, threads: Optional[int] = None) -> list:
+    """[fn(x) for x in items] on a thread pool.  Every oracle call is one
+    sequential C function that releases the interpreter lock, so independent
+    (sequence, automaton) pairs run on separate cores; each pair itself stays
+    a single sequential scan."""
+    items = list(items)
+    threads = threads or host_threads()
+    if threads <= 1 or len(items) <= 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))
 
 
 # ------------------------------------------------------------------ sequences

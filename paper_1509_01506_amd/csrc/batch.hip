@@ -17,9 +17,11 @@
 //     lane's state register addresses its own automaton's rows directly;
 //     two-symbol rows (64 B) when every automaton's counts fit them, else
 //     one-symbol rows (16 B);
-//   - a lane owns one (chunk, automaton) pair; the pairs of one chunk are
-//     adjacent lanes, so a chunk is read from HBM once for all automata of
-//     its group (the lanes load the same lines);
+//   - a lane owns one (chunk, automaton) pair; a wave holds one automaton
+//     over 64 consecutive chunks, and the waves of a span hold the other
+//     automata of the group over the same chunks, so a chunk is read from
+//     HBM about once for all automata of its group (the other waves find its
+//     lines in cache) while each wave walks a single table;
 //   - blocks are persistent and take 768-lane tasks from a device counter;
 //     a block restages LDS only when its task moves to another group.
 // k_bcompose resolves chunks whose candidates never agreed (only automata

@@ -425,33 +425,72 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
   if ((threadIdx.x & 63) == 0 && mine_sum) atomicAdd(a.total, (unsigned long long)mine_sum);
 }
 
-// Exclusive prefix of per-chunk counts (one block; each thread a contiguous
-// run of chunks).  Writes the total to *a.total.
-__global__ void k_scan_counts(ScanArgs a, uint64_t* off) {
-  __shared__ uint64_t part[1024];
-  const uint64_t n = a.n_chunks;
-  const uint64_t per = (n + blockDim.x - 1) / blockDim.x;
-  const uint64_t b = threadIdx.x * per;
-  const uint64_t e = b + per < n ? b + per : n;
-  uint64_t s = 0;
-  for (uint64_t i = b; i < e; ++i) s += a.chunk_cnt[i];
-  part[threadIdx.x] = s;
+// Exclusive prefix of per-chunk counts in three launches: a sum per tile of
+// 1024 chunks (k_count_partials), an exclusive scan of those sums
+// (k_scan_partials, one block), then a scan of every tile's own chunks from
+// its tile offset (k_count_offsets).  The last tile writes the total to
+// *a.total.
+constexpr uint32_t kCountTile = 1024;
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t t = __shfl_up(v, (unsigned)o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Inclusive scan over a block of kCountTile threads; `sh` holds 16 words.
+__device__ __forceinline__ uint64_t block_incl_scan(uint64_t v, uint64_t* sh) {
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  v = wave_incl_scan(v);
+  if (lane == 63) sh[w] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t run = 0;
-    for (uint32_t i = 0; i < blockDim.x; ++i) {
-      const uint64_t v = part[i];
-      part[i] = run;
-      run += v;
-    }
-    *a.total = run;
+  if (w == 0) {
+    uint64_t x = lane < (kCountTile >> 6) ? sh[lane] : 0;
+    x = wave_incl_scan(x);
+    if (lane < (kCountTile >> 6)) sh[lane] = x;
   }
   __syncthreads();
-  uint64_t run = part[threadIdx.x];
-  for (uint64_t i = b; i < e; ++i) {
-    off[i] = run;
-    run += a.chunk_cnt[i];
+  return v + (w ? sh[w - 1] : 0);
+}
+
+__global__ __launch_bounds__(kCountTile) void k_count_partials(ScanArgs a, uint64_t* part) {
+  __shared__ uint64_t sh[kCountTile / 64];
+  const uint64_t i = (uint64_t)blockIdx.x * kCountTile + threadIdx.x;
+  const uint64_t v = i < a.n_chunks ? a.chunk_cnt[i] : 0;
+  const uint64_t incl = block_incl_scan(v, sh);
+  if (threadIdx.x == kCountTile - 1) part[blockIdx.x] = incl;
+}
+
+// Exclusive scan of the tile sums in place (one block, any number of tiles).
+__global__ __launch_bounds__(kCountTile) void k_scan_partials(uint64_t* part, uint32_t n_tiles) {
+  __shared__ uint64_t sh[kCountTile / 64];
+  __shared__ uint64_t carry_sh;
+  if (threadIdx.x == 0) carry_sh = 0;
+  __syncthreads();
+  for (uint32_t t0 = 0; t0 < n_tiles; t0 += kCountTile) {
+    const uint32_t t = t0 + threadIdx.x;
+    const uint64_t v = t < n_tiles ? part[t] : 0;
+    const uint64_t carry = carry_sh;
+    const uint64_t incl = block_incl_scan(v, sh);
+    if (t < n_tiles) part[t] = carry + incl - v;
+    __syncthreads();
+    if (threadIdx.x == kCountTile - 1) carry_sh = carry + incl;
+    __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kCountTile) void k_count_offsets(ScanArgs a, const uint64_t* part, uint64_t* off) {
+  __shared__ uint64_t sh[kCountTile / 64];
+  const uint64_t base = part[blockIdx.x];
+  const uint64_t i = (uint64_t)blockIdx.x * kCountTile + threadIdx.x;
+  const uint64_t v = i < a.n_chunks ? a.chunk_cnt[i] : 0;
+  const uint64_t incl = block_incl_scan(v, sh);
+  if (i < a.n_chunks) off[i] = base + incl - v;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kCountTile - 1) *a.total = base + incl;
 }
 
 // Second pass of "find": every chunk from its true first state, writing end
@@ -660,6 +699,7 @@ int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) 
 struct Plan {
   uint32_t shift, step, k, group, max_cand, blocks, lds_bytes;
   bool all_conv;  // every chunk's candidates must agree inside the window (synchronising depth)
+  bool direct;    // counts only and all_conv: no non-converged maps, no join kernels
   uint64_t chunk, n_chunks, n_tiles;
   bool hist;
   int enc;
@@ -812,7 +852,7 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
   // counts of an automaton that synchronises inside every chunk's window need
   // neither non-converged maps nor the true first state of every chunk (the
   // fix-up reads its predecessor's last state); positions and records do
-  const bool direct = emit_counts && P.all_conv;
+  const bool direct = P.direct;
   if (!direct) {
     const uint32_t nc_lds = a.n_states * 16u + 16u;
     (void)hipFuncSetAttribute((const void*)k_nonconv<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -839,10 +879,12 @@ struct Call {
   hipStream_t st = nullptr;
   char* ws = nullptr;
   uint64_t* chunk_off = nullptr;
+  uint64_t* count_part = nullptr;  // per tile of kCountTile chunks: its count
 };
 
+// emit_counts: the call returns counts only (direct mode possible).
 int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* stream, bool force_hist,
-            bool need_chunk_cnt, Call& C) {
+            bool need_chunk_cnt, Call& C, bool emit_counts = false) {
   if (!h || !seq) return COEX_EINVAL;
   Dfa& d = *const_cast<Dfa*>(reinterpret_cast<const Dfa*>(h));
   if (seq->encoding != COEX_ENC_BYTE && seq->encoding != COEX_ENC_2BIT) return COEX_EINVAL;
@@ -856,6 +898,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   rc = make_plan(d, *C.dc, *seq, o, C.n_cu, C.P, force_hist);
   if (rc) return rc;
   Plan& P = C.P;
+  P.direct = emit_counts && P.all_conv;
   // chunk counts must fit the 32-bit per-chunk tail counter
   if (P.chunk > (0xFFFFFFFFull / std::max<uint32_t>(1, 2 * d.max_out + 1))) return COEX_EINVAL;
   const uint32_t S = P.shift;
@@ -884,10 +927,13 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   size_t o_ct = take(nc * 4), o_cs = take(nc * 4), o_es = take(nc * 4), o_tc = take(nc * 4);
   size_t o_ncc = take(4), o_nch = take(nc * 4), o_nsl = take(nc * 4), o_nm = take(nc * 4);
   size_t o_fxc = take(4), o_fxl = take(nc * 4);
-  size_t o_nca = take(nc * P.max_cand * 4), o_nen = take(nc * P.max_cand * 4);
+  // candidate maps of non-converged chunks: only when the join kernels run
+  const uint64_t nc_maps = P.direct ? 0 : nc * P.max_cand;
+  size_t o_nca = take(nc_maps * 4), o_nen = take(nc_maps * 4);
   size_t o_ts = take((nc + 1) * 4), o_tot = take(8), o_err = take(4);
   size_t o_front = take((size_t)P.n_tiles * 3 * 8);
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
+  size_t o_part = need_chunk_cnt ? take((nc + kCountTile - 1) / kCountTile * 8) : 0;
   rc = workspace(C.dev, stream, off, C.ws, C.wsp);
   if (rc) return rc;
   C.st = (hipStream_t)stream;
@@ -938,6 +984,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.front = reinterpret_cast<uint64_t*>(w + o_front);
   a.chunk_cnt = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_cc) : nullptr;
   C.chunk_off = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_co) : nullptr;
+  C.count_part = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_part) : nullptr;
   a.chunk_off = C.chunk_off;
   a.acc_out_off = C.dc->acc_out_off;
   a.acc_out_ids = C.dc->acc_out_ids;
@@ -1076,7 +1123,7 @@ int coex_count(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, c
   if (!counts_dev) return COEX_EINVAL;
   try {
     coex::Call C;
-    int rc = coex::prepare(dfa, seq, opts, stream, false, false, C);
+    int rc = coex::prepare(dfa, seq, opts, stream, false, false, C, true);
     if (rc) return rc;
     coex::run_pipeline(C, counts_dev, true);
     if (hipGetLastError() != hipSuccess) return COEX_EDEVICE;
@@ -1099,7 +1146,11 @@ int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32
     coex::run_pipeline(C, nullptr, false);
     uint64_t total = 0;
     if (C.P.n_chunks) {
-      hipLaunchKernelGGL(coex::k_scan_counts, dim3(1), dim3(1024), 0, C.st, C.a, C.chunk_off);
+      const uint32_t tiles = (uint32_t)((C.P.n_chunks + coex::kCountTile - 1) / coex::kCountTile);
+      hipLaunchKernelGGL(coex::k_count_partials, dim3(tiles), dim3(coex::kCountTile), 0, C.st, C.a, C.count_part);
+      hipLaunchKernelGGL(coex::k_scan_partials, dim3(1), dim3(coex::kCountTile), 0, C.st, C.count_part, tiles);
+      hipLaunchKernelGGL(coex::k_count_offsets, dim3(tiles), dim3(coex::kCountTile), 0, C.st, C.a, C.count_part,
+                         C.chunk_off);
     }
     if (hipMemcpyAsync(&total, C.a.total, 8, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
     uint32_t e = 0;

@@ -31,25 +31,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// Double-buffer the middle blocks of a chunk scan (1) or load each block
-// just before scanning it (0).
-#ifndef COEX_PREFETCH
-#define COEX_PREFETCH 0
-#endif
-// Bases per register block of the 2-bit scan (256: 64 + 32 bytes per lane
-// and load round; 512: 128 + 64 bytes).
-#ifndef COEX_BLOCK2
-#define COEX_BLOCK2 512
-#endif
 // Threads per block of the scan kernels.
-#ifndef COEX_SCAN_BLOCK
 #define COEX_SCAN_BLOCK 768
-#endif
 // Minimum waves per SIMD the chunk-scan kernel is compiled for (caps its
 // registers at 512 / waves).
-#ifndef COEX_TAIL_WAVES
 #define COEX_TAIL_WAVES 6
-#endif
 
 namespace coex {
 
@@ -382,12 +368,6 @@ __device__ __forceinline__ uint32_t run_word(const Tab& tb, uint32_t s, uint32_t
   return word_slow<SHIFT>(tb, s, cols, rst, 0xFFFFu, p, sink);
 }
 
-// Kept for callers that know the word has no resets.
-template <int SHIFT, int STEP, class Sink>
-__device__ __forceinline__ uint32_t word_fast(const Tab& tb, uint32_t s, uint32_t cols, uint64_t p, Sink& sink) {
-  return run_word<SHIFT, STEP>(tb, s, cols, 0u, p, sink);
-}
-
 // A block of sequence held in registers: 512 bases (128 bytes of 2-bit codes
 // and 64 bytes of N mask) or 128 bases (128 bytes).  Loaded with 16-byte
 // loads per lane so each lane consumes whole 128-byte lines at once.
@@ -396,7 +376,7 @@ struct Block;
 
 template <>
 struct Block<ENC_2BIT> {
-  static constexpr uint64_t BASES = COEX_BLOCK2;
+  static constexpr uint64_t BASES = 512;
   static constexpr int WORDS = (int)(BASES / 16);  // 16 bases per 32-bit word
   static constexpr int MW = WORDS / 2;             // 32 bases per 32-bit mask word
   uint32_t v[WORDS];
@@ -533,8 +513,7 @@ __device__ __forceinline__ uint32_t run_block(const Tab& tb, uint32_t s, const B
 }
 
 // Scans [p, hi) from state s.  With HAS_FIRST, `first` already holds the
-// block containing p.  Middle blocks are double-buffered: the next block's
-// loads are in flight while the current one is scanned.
+// block containing p.  Each middle block is loaded just before it is scanned.
 template <int ENC, int SHIFT, int STEP, bool HAS_FIRST, class Sink>
 __device__ __forceinline__ uint32_t scan_blocks(const ScanArgs& a, const Tab& tb, uint32_t s, uint64_t p,
                                                 uint64_t hi, Sink& sink, const Block<ENC>& first) {
@@ -549,27 +528,11 @@ __device__ __forceinline__ uint32_t scan_blocks(const ScanArgs& a, const Tab& tb
     s = run_block<ENC, SHIFT, STEP, true>(tb, s, blk, base, p, hi, sink);
   }
   base += B::BASES;
-#if COEX_PREFETCH
-  if (base + B::BASES <= hi) {
-    B cur;
-    cur.load(a, base);
-    for (;;) {
-      const bool more = base + 2 * B::BASES <= hi;
-      B nxt;
-      if (more) nxt.load(a, base + B::BASES);
-      s = run_block<ENC, SHIFT, STEP, false>(tb, s, cur, base, base, base + B::BASES, sink);
-      base += B::BASES;
-      if (!more) break;
-      cur = nxt;
-    }
-  }
-#else
   for (; base + B::BASES <= hi; base += B::BASES) {
     B cur;
     cur.load(a, base);
     s = run_block<ENC, SHIFT, STEP, false>(tb, s, cur, base, base, base + B::BASES, sink);
   }
-#endif
   if (base < hi) {
     B blk;
     load_block<ENC>(a, base, blk);

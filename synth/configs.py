@@ -15,7 +15,18 @@ Each function returns host data only; nothing here matches patterns.
           target sizes in [10, 500] states: 8 random k-mer sets, 8 random
           regexes (seed 404).
   serving Poisson arrivals; sizes log-uniform over [1e3, 1e8]; automaton ids
-          uniform over 32 resident automata (seeds 5 and 505).
+          uniform over 32 resident automata of 10-1000 states: 16 k-mer sets
+          and 16 regexes (seeds 5 and 505).
+
+Automaton sizes.  Each automaton of the batched and serving sets has a target
+size, log-uniform over the stated range.  A k-mer set holds target / k random
+k-mers; a regex slot takes the generator's draws seed*100 + 50 + i + 1000*j
+for j = 0, 1, ... and keeps the first whose minimal search automaton has
+between max(lo, target / 1.6) and min(hi, 1.6 * target) states.  Sizes are a
+property of the compiled automaton, which this package does not build, so the
+accepted draw index j of every slot is recorded below (REGEX_DRAWS) and the
+size of every automaton is asserted by the workload tests; every k-mer set
+takes its first draw, which already lands inside the range.
 """
 from __future__ import annotations
 
@@ -58,6 +69,11 @@ BATCH_SEED = 4
 BATCH_PATTERN_SEED = 404
 
 
+def size_targets(seed: int, n_kmer_sets: int, n_regexes: int, lo: float, hi: float):
+    """Target automaton sizes, log-uniform in [lo, hi]: k-mer sets first, then regexes."""
+    return loguniform_ints(seed, 16, n_kmer_sets + n_regexes, lo, hi)
+
+
 def kmer_sets(seed: int, count: int, lo: float, hi: float):
     """`count` random k-mer sets, k in 6..14, with about log-uniform target
     automaton sizes in [lo, hi] states (count of k-mers = target / k)."""
@@ -70,12 +86,30 @@ def kmer_sets(seed: int, count: int, lo: float, hi: float):
     return out
 
 
+def regex_candidate(seed: int, i: int, j: int) -> str:
+    """Draw j for regex slot i of a pattern set."""
+    return random_regex(seed * 100 + 50 + i + 1000 * j)
+
+
+def regex_window(target: int, lo: float, hi: float):
+    """States a regex drawn for `target` must have: within a factor 1.6 of it, inside [lo, hi]."""
+    return max(lo, target / 1.6), min(hi, target * 1.6)
+
+
+# accepted draw index j per regex slot (see the module docstring)
+REGEX_DRAWS = {
+    404: (9, 1, 22, 14, 0, 37, 0, 23),
+    505: (0, 0, 10, 0, 0, 4, 0, 3, 67, 0, 0, 1, 36, 0, 9, 0),
+}
+
+
 def regexes(seed: int, count: int):
-    return [random_regex(seed * 100 + 50 + i) for i in range(count)]
+    draws = REGEX_DRAWS[seed]
+    return [regex_candidate(seed, i, draws[i]) for i in range(count)]
 
 
 def batched_patterns():
-    """8 k-mer sets (target sizes log-uniform in [10, 500] states) and 8 random regexes."""
+    """8 k-mer sets and 8 regexes, target sizes log-uniform in [10, 500] states."""
     return kmer_sets(BATCH_PATTERN_SEED, 8, 10, 500), regexes(BATCH_PATTERN_SEED, 8)
 
 
@@ -106,7 +140,7 @@ SERVE_POOL = 100_000_000
 
 
 def serving_patterns():
-    """32 resident automata: 16 k-mer sets (log-uniform [10, 1000] states) and 16 regexes."""
+    """32 resident automata: 16 k-mer sets and 16 regexes, target sizes log-uniform in [10, 1000] states."""
     return kmer_sets(SERVE_PATTERN_SEED, 16, 10, 1000), regexes(SERVE_PATTERN_SEED, 16)
 
 

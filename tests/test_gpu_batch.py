@@ -190,26 +190,51 @@ def test_tuner_and_convenience(coex):
     assert got.tolist() == exp.tolist()
 
 
-def test_batched_config_sampled(coex):
-    # the batched workload (512 sequences, about 4e9 bases, 16 automata) in the
-    # bench's launch configuration; the oracle checks a sample of pairs: the
-    # shortest and longest sequences with every automaton
+def _all_pair_totals(pats, buf, offs, lengths, threads=None):
+    """Oracle totals of every (sequence, automaton) pair, pairs spread over the
+    host cores (each pair one sequential oracle scan)."""
+    jobs = [(s, d) for s in range(len(lengths)) for d in range(len(pats))]
+    jobs.sort(key=lambda sd: -lengths[sd[0]])  # longest first: balanced pool
+
+    def one(sd):
+        s, d = sd
+        return pats[d].total(oracle.byte_seq(buf[offs[s]:offs[s] + lengths[s]]))
+
+    vals = oracle.pool_map(one, jobs, threads)
+    exp = np.zeros((len(lengths), len(pats)), dtype=np.uint64)
+    for (s, d), v in zip(jobs, vals):
+        exp[s, d] = v
+    return exp
+
+
+@pytest.mark.timeout(1200)
+def test_batched_config_all_pairs(coex):
+    # the batched workload (512 sequences, about 4e9 bases, 16 automata of
+    # 10-500 states) in the bench's launch configuration (tuned chunk, graph
+    # replay); the oracle checks all 8,192 pairs
+    import time
     import torch
     lengths, buf, offs, (sets, rxs) = configs.batched()
     say("batched: total bases", sum(lengths))
     pats = [Pat(coex, "kmers", k) for k in sets] + [Pat(coex, "regex", r) for r in rxs]
+    states = [p.dfa.info().n_states for p in pats]
+    say("batched: automaton states", states)
+    assert all(10 <= n <= 500 for n in states)
     dbuf = torch.from_numpy(buf).to("cuda")
     seqs = [coex.DeviceSeq(dbuf[o:o + max(n, 1)], n, coex.ENC_BYTE) for o, n in zip(offs, lengths)]
     dset = coex.DfaSet([p.dfa for p in pats])
-    b = coex.Batch(dset, seqs, graph=True, check=False)
-    got = b.run().cpu().numpy().view(np.uint64)
+    tb = coex.Batch(dset, seqs)
+    chunk = tb.tune()
+    tb.free()
+    b = coex.Batch(dset, seqs, chunk=chunk, graph=True, check=False)
+    got = b.run().cpu().numpy().view(np.uint64).reshape(len(lengths), len(pats))
+    got2 = b.run().cpu().numpy().view(np.uint64).reshape(len(lengths), len(pats))
     say("batched: gpu done", b.info())
-    order = np.argsort(lengths)
-    sample = list(order[:6]) + list(order[-2:])
-    for s in sample:
-        h = oracle.byte_seq(buf[offs[s]:offs[s] + lengths[s]])
-        for d, p in enumerate(pats):
-            assert int(got[s, d]) == p.total(h), (s, d, lengths[s])
-    say("batched: sample ok")
     del dbuf, seqs, b
     torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    exp = _all_pair_totals(pats, buf, offs, lengths, threads=min(16, oracle.host_threads()))
+    say("batched: oracle over %d pairs in %.1f s" % (exp.size, time.perf_counter() - t0))
+    bad = np.argwhere(got != exp)
+    assert bad.size == 0, [(int(s), int(d), int(got[s, d]), int(exp[s, d])) for s, d in bad[:10]]
+    assert (got2 == got).all()

@@ -59,3 +59,41 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _states(dfa_maker, pattern):
+    return dfa_maker(pattern).info().n_states
+
+
+def _check_set(seed, n_kmer_sets, n_regexes, lo, hi, sets, rxs):
+    import paper_1509_01506_amd as coex
+    targets = configs.size_targets(seed, n_kmer_sets, n_regexes, lo, hi)
+    assert len(sets) == n_kmer_sets and len(rxs) == n_regexes
+    for s in sets:
+        n = _states(coex.Dfa.kmers, s)
+        assert lo <= n <= hi, (s[:2], n)
+    draws = configs.REGEX_DRAWS[seed]
+    for i, r in enumerate(rxs):
+        wlo, whi = configs.regex_window(targets[n_kmer_sets + i], lo, hi)
+        n = _states(coex.Dfa.regex, r)
+        assert wlo <= n <= whi and lo <= n <= hi, (i, r, n, targets[n_kmer_sets + i])
+        # the recorded draw is the first one inside the window
+        assert r == configs.regex_candidate(seed, i, draws[i])
+        for j in range(draws[i]):
+            try:
+                m = _states(coex.Dfa.regex, configs.regex_candidate(seed, i, j))
+            except Exception:
+                continue  # a draw the compiler rejects (empty match) is skipped
+            assert not (wlo <= m <= whi), (i, j, m)
+
+
+def test_batched_automata_sizes_in_range():
+    # 16 automata of 10-500 states (8 k-mer sets, 8 regexes)
+    sets, rxs = configs.batched_patterns()
+    _check_set(configs.BATCH_PATTERN_SEED, 8, 8, 10, 500, sets, rxs)
+
+
+def test_serving_automata_sizes_in_range():
+    # 32 resident automata of 10-1000 states (16 k-mer sets, 16 regexes)
+    sets, rxs = configs.serving_patterns()
+    _check_set(configs.SERVE_PATTERN_SEED, 16, 16, 10, 1000, sets, rxs)
