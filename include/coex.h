@@ -57,6 +57,8 @@ extern "C" {
 #define COEX_EUNSUPPORTED (-7)/* option combination not supported */
 #define COEX_ESYNTAX (-8)     /* regular expression syntax error, or it matches the empty string */
 #define COEX_EINTERNAL (-9)   /* a device-side consistency check failed */
+#define COEX_ESCRATCH (-10)   /* coex_count_noalloc: the call needs more than its static scratch array */
+#define COEX_ENOTRESIDENT (-11) /* coex_count_noalloc: the automaton's tables are not yet on this device */
 
 /* ------------------------------------------------------- sequence formats */
 #define COEX_ENC_BYTE 0  /* one ASCII byte per base */
@@ -157,6 +159,27 @@ void coex_dfa_free(coex_dfa* dfa);
    Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int coex_count(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, const coex_opts* opts,
                void* stream);
+
+/* coex_count for callers that cannot allocate device memory: code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+   arguments, plan, kernels and results as coex_count, but the call makes no
+   hipMalloc, hipFree or other allocating call: its scratch (per-chunk
+   converging points, states and counts, the fix-up list and, for automata
+   that can leave a chunk unconverged, the candidate maps) lives in one static
+   device array of 64 MiB per GPU, held from library load to process exit.
+   That covers every planner-chosen chunking of an automaton whose chunks
+   always converge (about 36 bytes per chunk); a call whose plan needs more
+   returns ESCRATCH before launching anything.  Device counters are cleared by
+   a kernel at the start of every call, so no state carries over from the
+   previous call, but every call on one GPU shares that GPU's array: calls
+   that overlap on one GPU (other streams, other threads) race and must be
+   serialised by the caller.  The automaton's tables must already be on the
+   current device (any earlier coex_count, coex_find or coex_count_chunks on
+   that device puts them there), else ENOTRESIDENT.  COEX_FLAG_TIME is not
+   supported (EUNSUPPORTED); COEX_FLAG_CHECK synchronises as for coex_count.
+   Errors: EINVAL, ENOTRESIDENT, ESCRATCH, EUNSUPPORTED, EDEVICE. */
+int coex_count_noalloc(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, const coex_opts* opts,
+                       void* stream);
 
 /* End positions of every match ("count and extract", Section III.A):
    pos_dev int64[capacity] and pattern_dev uint32[capacity] (may be NULL)

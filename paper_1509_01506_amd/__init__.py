@@ -24,10 +24,12 @@ FLAG_TIME = 2
 FLAG_GRAPH = 4
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -5: "ECAPACITY",
-          -6: "EDEVICE", -7: "EUNSUPPORTED", -8: "ESYNTAX", -9: "EINTERNAL"}
+          -6: "EDEVICE", -7: "EUNSUPPORTED", -8: "ESYNTAX", -9: "EINTERNAL", -10: "ESCRATCH",
+          -11: "ENOTRESIDENT"}
 
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
-            "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_find", "coex_count_chunks",
+            "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_count_noalloc", "coex_find",
+            "coex_count_chunks",
             "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
             "coex_batch_update", "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free",
             "coex_server_create", "coex_server_submit", "coex_server_wait", "coex_server_stats", "coex_server_free",
@@ -102,6 +104,7 @@ def _lib():
         L.coex_dfa_free.argtypes = [p]
         L.coex_dfa_free.restype = None
         L.coex_count.argtypes = [p, p, p, p, p]
+        L.coex_count_noalloc.argtypes = [p, p, p, p, p]
         L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
         L.coex_count_chunks.argtypes = [p, p, u32, p, p, p, p]
         L.coex_count_batched.argtypes = [p, u32, p, u32, p, p, p]
@@ -278,6 +281,20 @@ def count(dfa: Dfa, seq: DeviceSeq, out=None, chunk: int = 0, width: int = 0, lo
     o = _opts(chunk, width, lookback, step, check, timed)
     _check(_lib().coex_count(dfa.handle, ctypes.byref(s), out.data_ptr(), ctypes.byref(o), _stream(stream)),
            "count")
+    return out[:P]
+
+
+def count_noalloc(dfa: Dfa, seq: DeviceSeq, out, chunk: int = 0, width: int = 0, lookback: int = 0,
+                  step: int = 0, check: bool = False, stream=None):
+    """count() through coex_count_noalloc: the library allocates nothing (its
+    scratch is a static device array); `out` is the caller's int64 tensor."""
+    P = dfa.info().n_patterns
+    if out.numel() < P or str(out.dtype) != "torch.int64" or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 tensor of at least %d elements" % P)
+    s = seq._c()
+    o = _opts(chunk, width, lookback, step, check)
+    _check(_lib().coex_count_noalloc(dfa.handle, ctypes.byref(s), out.data_ptr(), ctypes.byref(o),
+                                     _stream(stream)), "count_noalloc")
     return out[:P]
 
 

@@ -525,6 +525,13 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(ScanArgs a) {
 }
 
 // ====================================================================== host runtime
+// Scratch of coex_count_noalloc: one array per GPU, placed by the code object
+// loader, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host it names a stand-in, not the device
+// address): the address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 struct DeviceCopy {
   int device = -1;
   char* buf = nullptr;
@@ -672,6 +679,31 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
   if ((int)d.dev.size() <= dev) d.dev.resize(dev + 1, nullptr);
   d.dev[dev] = dc.release();
   out = d.dev[dev];
+  return COEX_OK;
+}
+
+// The device copy of an automaton's tables if it already exists (no upload).
+int resident(Dfa& d, int dev, DeviceCopy*& out) {
+  std::lock_guard<std::mutex> lk(d.mu);
+  if ((int)d.dev.size() > dev && d.dev[dev]) { out = d.dev[dev]; return COEX_OK; }
+  return COEX_ENOTRESIDENT;
+}
+
+// Device address of this GPU's static scratch array, looked up once per
+// device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_at[kMaxDevices] = {};
+
+int static_scratch(int dev, char*& out) {
+  if (dev < 0 || dev >= kMaxDevices) return COEX_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return COEX_EDEVICE;
+    g_scratch_at[dev] = static_cast<char*>(p);
+  }
+  out = g_scratch_at[dev];
   return COEX_OK;
 }
 
@@ -883,8 +915,9 @@ struct Call {
 };
 
 // emit_counts: the call returns counts only (direct mode possible).
+// noalloc: tables must already be resident, scratch is the static array.
 int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* stream, bool force_hist,
-            bool need_chunk_cnt, Call& C, bool emit_counts = false) {
+            bool need_chunk_cnt, Call& C, bool emit_counts = false, bool noalloc = false) {
   if (!h || !seq) return COEX_EINVAL;
   Dfa& d = *const_cast<Dfa*>(reinterpret_cast<const Dfa*>(h));
   if (seq->encoding != COEX_ENC_BYTE && seq->encoding != COEX_ENC_2BIT) return COEX_EINVAL;
@@ -893,7 +926,8 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   if (hipGetDevice(&C.dev) != hipSuccess) return COEX_EDEVICE;
   int rc = dev_props(C.dev, C.n_cu);
   if (rc) return rc;
-  rc = upload(d, C.dev, C.dc);
+  if (noalloc && o && (o->flags & COEX_FLAG_TIME)) return COEX_EUNSUPPORTED;  // timing creates events
+  rc = noalloc ? resident(d, C.dev, C.dc) : upload(d, C.dev, C.dc);
   if (rc) return rc;
   rc = make_plan(d, *C.dc, *seq, o, C.n_cu, C.P, force_hist);
   if (rc) return rc;
@@ -934,7 +968,13 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   size_t o_front = take((size_t)P.n_tiles * 3 * 8);
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
   size_t o_part = need_chunk_cnt ? take((nc + kCountTile - 1) / kCountTile * 8) : 0;
-  rc = workspace(C.dev, stream, off, C.ws, C.wsp);
+  if (noalloc) {
+    if (off > kStaticScratchBytes) return COEX_ESCRATCH;
+    rc = static_scratch(C.dev, C.ws);
+    C.wsp = nullptr;
+  } else {
+    rc = workspace(C.dev, stream, off, C.ws, C.wsp);
+  }
   if (rc) return rc;
   C.st = (hipStream_t)stream;
   C.timed = o && (o->flags & COEX_FLAG_TIME);
@@ -1136,6 +1176,24 @@ int coex_count(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, c
   }
 }
 
+int coex_count_noalloc(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, const coex_opts* opts,
+                       void* stream) {
+  if (!counts_dev) return COEX_EINVAL;
+  try {
+    coex::Call C;
+    int rc = coex::prepare(dfa, seq, opts, stream, false, false, C, true, true);
+    if (rc) return rc;
+    coex::run_pipeline(C, counts_dev, true);
+    if (hipGetLastError() != hipSuccess) return COEX_EDEVICE;
+    if (opts && (opts->flags & COEX_FLAG_CHECK)) return coex::check_err(C);
+    return COEX_OK;
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
 int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
               uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream) {
   if (!n_found || (capacity && !pos_dev)) return COEX_EINVAL;
@@ -1222,6 +1280,8 @@ const char* coex_strerror(int s) {
     case COEX_EUNSUPPORTED: return "unsupported option combination";
     case COEX_ESYNTAX: return "regular expression syntax error or empty match";
     case COEX_EINTERNAL: return "device consistency check failed";
+    case COEX_ESCRATCH: return "call needs more scratch than the static array of coex_count_noalloc holds";
+    case COEX_ENOTRESIDENT: return "automaton tables not yet on this device (any allocating scan call puts them there)";
     default: return "unknown status";
   }
 }
