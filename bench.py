@@ -407,6 +407,10 @@ def main():
                     help="untimed steps for this many seconds before the warm-up steps (sustained clocks)")
     ap.add_argument("--copy-piece-mib", type=int, default=0,
                     help="serving: bytes per host-to-device copy piece in MiB (0 = the library's default)")
+    ap.add_argument("--step", type=int, default=0,
+                    help="symbols per table lookup in the chunk scan (0 = the planner's choice; 1, 2 or 3)")
+    ap.add_argument("--chunk", type=int, default=0, help="bases per chunk (0 = the workload's or the planner's)")
+    ap.add_argument("--chains", type=int, default=0, help="chunks walked per lane at once (0 = the planner's choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -447,10 +451,12 @@ def main():
 
     out = torch.empty(max(1, info.n_patterns), dtype=torch.int64, device="cuda")
 
+    chunk = args.chunk or w["chunk"]
+
     def step(timed: bool):
-        coex.count(dfa, seq, out=out, chunk=w["chunk"], timed=timed)
+        coex.count(dfa, seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains)
         if w["find"]:
-            coex.find(dfa, seq, chunk=w["chunk"])
+            coex.find(dfa, seq, chunk=chunk, step=args.step, chains=args.chains)
 
     # untimed: bring the GPU to its sustained clocks (about half a second of
     # steps), then the W warm-up steps of the contract
@@ -485,8 +491,14 @@ def main():
 
     algo_bytes = w["n"] * w["bytes_per_base"]
     achieved = algo_bytes / (k_avg_ms * 1e-3) / 1e9
-    sym = 2 if info.n_states <= 1024 else 1  # the planner's default table for the chunk scan
-    lookups_per_clk = w["n"] / sym / (k_avg_ms * 1e-3) / (256 * 2.4e9)
+    # symbols per lookup of the chunk scan (the planner's default: three for
+    # 2-bit input of an automaton of at most 1023 states, else two, else one)
+    sym = args.step or (1 if info.n_states > 1024 else (3 if w["enc"] == coex.ENC_2BIT and info.n_states <= 1023
+                                                         else 2))
+    # lookups per base: three symbols per lookup walk 512-base blocks as ten
+    # 48-base units (16 lookups) and two words (5 three- + 1 one-symbol lookup)
+    per_base = {1: 1.0, 2: 0.5, 3: 172.0 / 512.0}[sym]
+    lookups_per_clk = w["n"] * per_base / (k_avg_ms * 1e-3) / (256 * 2.4e9)
     traffic = measured_traffic(args.workload)
     res = {
         "metric": "Gbases/s scanned (exact counts)",

@@ -84,17 +84,22 @@ typedef struct {
              from all of them to its end instead
    lookback: k, the number of bases before a chunk used to narrow its possible
              starting states (1 = the paper's single last symbol; 1..8)
-   step:     symbols per table lookup in the main loop (1 or 2; 2 needs at
-             most 1024 states)
+   step:     symbols per table lookup in the main loop (1, 2 or 3; 2 needs at
+             most 1024 states, 3 at most 1023: five three-symbol lookups and
+             one one-symbol lookup per 16 bases)
    flags:    COEX_FLAG_CHECK: synchronise the stream at the end of the call and
              return COEX_EINTERNAL if a device-side consistency check failed;
-             COEX_FLAG_TIME: time the scan kernel (coex_profile) */
+             COEX_FLAG_TIME: time the scan kernel (coex_profile)
+   chains:   chunks one lane walks at once, their table lookups interleaved
+             so that several dependent chains of reads are in flight (1 or 2;
+             2 needs step 2 or 3) */
 typedef struct {
   uint32_t chunk;
   uint32_t width;
   uint32_t lookback;
   uint32_t step;
   uint32_t flags;
+  uint32_t chains;
 } coex_opts;
 
 #define COEX_FLAG_CHECK 1u
@@ -197,6 +202,24 @@ int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32
    counts_dev: uint64[n_chunks * n_patterns].  Asynchronous. */
 int coex_count_chunks(const coex_dfa* dfa, const coex_seq* seq, uint32_t chunk, uint32_t* init_dev,
                       uint32_t* last_dev, uint64_t* counts_dev, void* stream);
+
+/* The paper's own method on the host's cores (Section III, Algorithm 1), a
+   CPU baseline reported beside the GPU scan (never used by the calls above):
+   `n_chunks` equal chunks (0 = one per thread; the last takes the remainder)
+   taken by `threads` worker threads (0 = every hardware thread).  Per chunk:
+   possible starting states from the symbol before it (Section III.A), the
+   first candidate's run R0 over the whole chunk with its state after each of
+   the first `window` symbols kept (0 = 4096), every other candidate run
+   until it meets R0 after the same number of symbols (the converging point,
+   Section III.B.3) or, failing that inside the window, to the chunk end; then
+   the join links each chunk's last state to the next chunk's first state and
+   the counts are fixed up at the converging point.  Host pointers: bases
+   (n_bases bytes, or packed 2-bit codes with the optional n_mask, as
+   coex_seq describes), counts uint64[n_patterns].  Synchronous.  Errors:
+   EINVAL, ENOMEM, EINTERNAL (the true first state missing from a chunk's
+   possible starting states, which the method rules out). */
+int coex_count_host(const coex_dfa* dfa, const void* bases, const uint8_t* n_mask, uint64_t n_bases,
+                    int32_t encoding, uint32_t threads, uint64_t n_chunks, uint64_t window, uint64_t* counts);
 
 /* ------------------------------------------------------------ batches
    Many sequences and automata in one persistent launch.  Per pair the method

@@ -29,7 +29,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -
 
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_count_noalloc", "coex_find",
-            "coex_count_chunks",
+            "coex_count_chunks", "coex_count_host",
             "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
             "coex_batch_update", "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free",
             "coex_server_create", "coex_server_submit", "coex_server_wait", "coex_server_stats", "coex_server_free",
@@ -51,7 +51,7 @@ class _Seq(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("width", ctypes.c_uint32), ("lookback", ctypes.c_uint32),
-                ("step", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("step", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("chains", ctypes.c_uint32)]
 
 
 class _Info(ctypes.Structure):
@@ -94,6 +94,11 @@ def _lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libcoex.so is not built (run __graft_entry__.build() or "
                               "python paper_1509_01506_amd/build.py)")
+        # torch first: the HIP runtime it loads is then the one libcoex.so
+        # binds to (the same soname), so the device memory and streams torch
+        # hands over belong to the library's runtime too; loading libcoex.so
+        # first would bring in a second HIP runtime beside torch's
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         p, u32, u64, ci = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
         L.coex_compile_kmers.argtypes = [p, u32, p]
@@ -105,6 +110,7 @@ def _lib():
         L.coex_dfa_free.restype = None
         L.coex_count.argtypes = [p, p, p, p, p]
         L.coex_count_noalloc.argtypes = [p, p, p, p, p]
+        L.coex_count_host.argtypes = [p, p, p, u64, ctypes.c_int32, u32, u64, u64, p]
         L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
         L.coex_count_chunks.argtypes = [p, p, u32, p, p, p, p]
         L.coex_count_batched.argtypes = [p, u32, p, u32, p, p, p]
@@ -255,9 +261,9 @@ def to_device(data: np.ndarray, n: Optional[int] = None, encoding: int = ENC_BYT
     return DeviceSeq(b, int(n), encoding, m)
 
 
-def _opts(chunk=0, width=0, lookback=0, step=0, check=False, timed=False, graph=False) -> _Opts:
+def _opts(chunk=0, width=0, lookback=0, step=0, check=False, timed=False, graph=False, chains=0) -> _Opts:
     return _Opts(chunk, width, lookback, step,
-                 (FLAG_CHECK if check else 0) | (FLAG_TIME if timed else 0) | (FLAG_GRAPH if graph else 0))
+                 (FLAG_CHECK if check else 0) | (FLAG_TIME if timed else 0) | (FLAG_GRAPH if graph else 0), chains)
 
 
 def _stream(stream):
@@ -269,7 +275,7 @@ def _stream(stream):
 
 # ------------------------------------------------------------------ scans
 def count(dfa: Dfa, seq: DeviceSeq, out=None, chunk: int = 0, width: int = 0, lookback: int = 0, step: int = 0,
-          check: bool = False, timed: bool = False, stream=None):
+          check: bool = False, timed: bool = False, stream=None, chains: int = 0):
     """Per-pattern match counts as an int64 CUDA tensor (the device buffer holds uint64)."""
     import torch
     P = dfa.info().n_patterns
@@ -278,33 +284,33 @@ def count(dfa: Dfa, seq: DeviceSeq, out=None, chunk: int = 0, width: int = 0, lo
     if out.numel() < P or out.dtype != torch.int64 or not out.is_contiguous():
         raise ValueError("out must be a contiguous int64 tensor of at least %d elements" % P)
     s = seq._c()
-    o = _opts(chunk, width, lookback, step, check, timed)
+    o = _opts(chunk, width, lookback, step, check, timed, chains=chains)
     _check(_lib().coex_count(dfa.handle, ctypes.byref(s), out.data_ptr(), ctypes.byref(o), _stream(stream)),
            "count")
     return out[:P]
 
 
 def count_noalloc(dfa: Dfa, seq: DeviceSeq, out, chunk: int = 0, width: int = 0, lookback: int = 0,
-                  step: int = 0, check: bool = False, stream=None):
+                  step: int = 0, check: bool = False, stream=None, chains: int = 0):
     """count() through coex_count_noalloc: the library allocates nothing (its
     scratch is a static device array); `out` is the caller's int64 tensor."""
     P = dfa.info().n_patterns
     if out.numel() < P or str(out.dtype) != "torch.int64" or not out.is_contiguous():
         raise ValueError("out must be a contiguous int64 tensor of at least %d elements" % P)
     s = seq._c()
-    o = _opts(chunk, width, lookback, step, check)
+    o = _opts(chunk, width, lookback, step, check, chains=chains)
     _check(_lib().coex_count_noalloc(dfa.handle, ctypes.byref(s), out.data_ptr(), ctypes.byref(o),
                                      _stream(stream)), "count_noalloc")
     return out[:P]
 
 
 def find(dfa: Dfa, seq: DeviceSeq, capacity: Optional[int] = None, chunk: int = 0, width: int = 0,
-         lookback: int = 0, step: int = 0, stream=None):
+         lookback: int = 0, step: int = 0, stream=None, chains: int = 0):
     """(end positions int64, pattern ids int32) CUDA tensors, ascending."""
     import torch
     dev = seq.bases.device
     s = seq._c()
-    o = _opts(chunk, width, lookback, step)
+    o = _opts(chunk, width, lookback, step, chains=chains)
     n_found = ctypes.c_uint64(0)
     if capacity is None:
         # a first guess that holds most results, so the scan usually runs once
@@ -325,6 +331,21 @@ def find(dfa: Dfa, seq: DeviceSeq, capacity: Optional[int] = None, chunk: int = 
     _check(rc, "find")
     m = int(n_found.value)
     return pos[:m], pat[:m]
+
+
+def count_host(dfa: Dfa, data: np.ndarray, n: Optional[int] = None, encoding: int = ENC_BYTE,
+               nmask: Optional[np.ndarray] = None, threads: int = 0, chunks: int = 0, window: int = 0) -> np.ndarray:
+    """The paper's method on host threads (coex_count_host): per-pattern
+    counts (uint64 numpy array) of a host sequence."""
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    if n is None:
+        n = data.size if encoding == ENC_BYTE else data.size * 4
+    m = np.ascontiguousarray(nmask, dtype=np.uint8) if nmask is not None else None
+    out = np.zeros(max(1, dfa.info().n_patterns), dtype=np.uint64)
+    _check(_lib().coex_count_host(dfa.handle, data.ctypes.data if data.size else None,
+                                  m.ctypes.data if m is not None else None, int(n), int(encoding), int(threads),
+                                  int(chunks), int(window), out.ctypes.data), "count_host")
+    return out[:dfa.info().n_patterns]
 
 
 def count_chunks(dfa: Dfa, seq: DeviceSeq, chunk: int, stream=None):

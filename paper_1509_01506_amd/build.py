@@ -45,7 +45,9 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     sfx = tag.replace(".", "_")
     obj_host = os.path.join(CSRC, "compile%s.o" % sfx)
     obj_serve = os.path.join(CSRC, "serve%s.o" % sfx)
-    dev_srcs = ["coex.hip", "batch.hip"]
+    obj_hm = os.path.join(CSRC, "host_method%s.o" % sfx)
+    dev_srcs = ["coex.hip", "batch.hip"] + ["tail_%s_%s.hip" % (e, k) for e in ("byte", "2bit")
+                                            for k in ("count", "hist")]
     obj_dev = [os.path.join(CSRC, "%s%s.o" % (os.path.splitext(f)[0], sfx)) for f in dev_srcs]
     tmp = out + tag
     try:
@@ -55,6 +57,9 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
                 subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-D__HIP_PLATFORM_AMD__",
                                   "-I/opt/rocm/include", "-c", "-o", obj_serve] + inc +
                                  [os.path.join(CSRC, "serve.cpp")],
+                                 stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True),
+                subprocess.Popen(["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-c", "-o", obj_hm] + inc +
+                                 [os.path.join(CSRC, "host_method.cpp")],
                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)]
         for src, obj in zip(dev_srcs, obj_dev):
             cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + inc + ["-c", "-o", obj, os.path.join(CSRC, src)]
@@ -72,11 +77,11 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
         if errs:
             raise RuntimeError("compile failed:\n" + "\n".join(errs))
         rocm_lib = "/opt/rocm/lib"
-        _run(["g++", "-shared", "-pthread", "-o", tmp] + obj_dev + [obj_host, obj_serve, "-L" + rocm_lib,
+        _run(["g++", "-shared", "-pthread", "-o", tmp] + obj_dev + [obj_host, obj_serve, obj_hm, "-L" + rocm_lib,
               "-lamdhip64", "-Wl,-rpath," + rocm_lib], verbose)
         os.replace(tmp, out)
     finally:
-        for f in [obj_host, obj_serve, tmp] + obj_dev:
+        for f in [obj_host, obj_serve, obj_hm, tmp] + obj_dev:
             if os.path.exists(f):
                 os.remove(f)
     return out

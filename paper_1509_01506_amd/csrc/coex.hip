@@ -37,18 +37,11 @@
 #include "coex.h"
 #include "dfa.hpp"
 #include "kernels.hpp"
+#include "tail.hpp"
 
 namespace coex {
 
 // ====================================================================== kernels
-constexpr int kScanBlock = COEX_SCAN_BLOCK;
-
-__device__ __forceinline__ void copy_to_lds(char* dst, const void* src, uint32_t bytes) {
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  uint4* d = reinterpret_cast<uint4*>(dst);
-  for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
-}
-
 __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
@@ -59,257 +52,6 @@ __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
   }
   if (counts)
     for (uint32_t i = t; i < n_counts; i += gridDim.x * blockDim.x) counts[i] = 0;
-}
-
-// First SPEC_WIN symbols of [lo, hi) for block-unaligned chunk starts
-// (aligned starts take them from the chunk's first block).
-template <int ENC>
-__device__ __forceinline__ void stage_symbols(const ScanArgs& a, uint64_t lo, uint64_t hi, uint64_t& sy0,
-                                              uint64_t& sy1, uint64_t& rs) {
-  uint32_t c[4] = {0, 0, 0, 0}, r[4] = {0, 0, 0, 0};
-  for (uint32_t i = 0; i < SPEC_WIN && lo + i < hi; ++i) {
-    const int col = load_col<ENC>(a, lo + i);
-    const uint32_t bit = col < 0 ? 0u : (uint32_t)col;
-    const uint32_t w = i >> 4, sh = 2 * (i & 15), rb = col < 0 ? 1u << (i & 15) : 0u;
-    c[0] |= w == 0 ? bit << sh : 0u;
-    c[1] |= w == 1 ? bit << sh : 0u;
-    c[2] |= w == 2 ? bit << sh : 0u;
-    c[3] |= w == 3 ? bit << sh : 0u;
-    r[0] |= w == 0 ? rb : 0u;
-    r[1] |= w == 1 ? rb : 0u;
-    r[2] |= w == 2 ? rb : 0u;
-    r[3] |= w == 3 ? rb : 0u;
-  }
-  sy0 = (uint64_t)c[0] | ((uint64_t)c[1] << 32);
-  sy1 = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
-  rs = (uint64_t)r[0] | ((uint64_t)r[1] << 16) | ((uint64_t)r[2] << 32) | ((uint64_t)r[3] << 48);
-}
-
-// First SPEC_WIN symbols of a chunk starting at lo with lo % 64 == 0 and
-// lo + 64 <= n: one 16-byte load of codes and one 8-byte load of N bits
-// (2-bit), or four 16-byte loads (bytes).
-template <int ENC>
-__device__ __forceinline__ void front_symbols(const ScanArgs& a, uint64_t lo, uint64_t& sy0, uint64_t& sy1,
-                                              uint64_t& rs) {
-  if constexpr (ENC == ENC_2BIT) {
-    const uint4 v = *reinterpret_cast<const uint4*>(a.bases + (lo >> 2));
-    sy0 = (uint64_t)v.x | ((uint64_t)v.y << 32);
-    sy1 = (uint64_t)v.z | ((uint64_t)v.w << 32);
-    if (a.nmask) {
-      const uint2 mm = *reinterpret_cast<const uint2*>(a.nmask + (lo >> 3));
-      rs = (uint64_t)mm.x | ((uint64_t)mm.y << 32);
-    } else {
-      rs = 0;
-    }
-  } else {
-    Block<ENC_BYTE> b;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) b.r[i] = *reinterpret_cast<const uint4*>(a.bases + lo + 16 * i);
-    uint32_t c[4], r[4];
-#pragma unroll
-    for (int w = 0; w < 4; ++w) b.word(w, c[w], r[w]);
-    sy0 = (uint64_t)c[0] | ((uint64_t)c[1] << 32);
-    sy1 = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
-    rs = (uint64_t)r[0] | ((uint64_t)r[1] << 16) | ((uint64_t)r[2] << 32) | ((uint64_t)r[3] << 48);
-  }
-}
-
-// Runs `count` (<= SPEC_WIN) staged symbols from s.
-template <int SHIFT, class Sink>
-__device__ __forceinline__ uint32_t run_staged(const Tab& tb, uint32_t s, uint64_t sy0, uint64_t sy1, uint64_t rs,
-                                               uint32_t count, uint64_t p, Sink& sink) {
-  for (uint32_t t = 0; t < count; ++t) {
-    const int col = (rs & 1u) ? -1 : (int)(sy0 & 3u);
-    s = step1<SHIFT>(tb, s, col, p + t, sink);
-    sy0 = (sy0 >> 2) | (sy1 << 62);
-    sy1 >>= 2;
-    rs >>= 1;
-  }
-  return s;
-}
-
-// Speculation for one tile of 64 chunks (one wave): possible starting states
-// from the lookback table, then rounds in which G lanes run the candidates
-// of one chunk in lockstep over its first symbols until they agree (the
-// converging point of Algorithm 1).  Writes conv_t / conv_s per chunk (and
-// returns this lane's pair), or queues the chunk as non-converged.
-template <int ENC, int SHIFT>
-__device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, const uint32_t* pss_off,
-                                          const uint16_t* pss_states, uint64_t tile_id, uint32_t& out_t,
-                                          uint32_t& out_s) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t c = tile_id * TILE + lane;
-  const bool valid = c < a.n_chunks;
-  const uint64_t lo = valid ? c * a.chunk : 0;
-  const uint64_t hi = valid ? (lo + a.chunk < a.n ? lo + a.chunk : a.n) : 0;
-  uint32_t m = 0, cbase = 0, exact = 0;
-  bool is_exact = false;
-  uint64_t sy0 = 0, sy1 = 0, rs = 0;
-  if (valid) {
-    if ((lo & 63) == 0 && lo + SPEC_WIN <= a.n) front_symbols<ENC>(a, lo, sy0, sy1, rs);
-    else stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
-    chunk_header<ENC, SHIFT>(a, tb, pss_off, lo, m, cbase, exact, is_exact);
-  }
-  const uint32_t len = (uint32_t)((hi - lo) < SPEC_WIN ? (hi - lo) : SPEC_WIN);
-  const uint32_t G = a.group;
-  const uint32_t R = 64u / G;
-  const uint32_t gidx = lane / G, gi = lane % G, gl = lane & ~(G - 1);
-  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-  uint32_t my_t = NONCONV, my_s = 0;
-  for (uint32_t r = 0; r < G; ++r) {
-    const int owner = (int)(r * R + gidx);
-    const uint32_t om = __shfl(m, owner);
-    const uint32_t ocb = __shfl(cbase, owner);
-    const uint32_t oex = __shfl(exact, owner);
-    const int oisx = __shfl((int)is_exact, owner);
-    const uint32_t olen = __shfl(len, owner);
-    uint64_t o0 = __shfl(sy0, owner), o1 = __shfl(sy1, owner), orr = __shfl(rs, owner);
-    const bool act = om > 0 && om <= G;
-    uint32_t s = tb.q0s;
-    if (act) s = oisx ? oex : ((uint32_t)pss_states[ocb + (gi < om ? gi : om - 1)] << SHIFT);
-    uint32_t res_t = NONCONV, res_s = 0;
-    for (uint32_t t = 0; t <= (uint32_t)SPEC_WIN; ++t) {
-      const uint32_t lead = __shfl(s, (int)gl);
-      const unsigned long long ne = __ballot(act && s != lead);
-      const bool gdone = ((ne >> gl) & gmask) == 0;
-      if (act && gdone && res_t == NONCONV && t <= olen) { res_t = t; res_s = s; }
-      const bool pending = act && res_t == NONCONV && t < olen;
-      if (__ballot(pending) == 0) break;
-      const int col = (orr & 1u) ? -1 : (int)(o0 & 3u);
-      s = col < 0 ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (uint32_t)col) & 0xFFFFu);
-      o0 = (o0 >> 2) | (o1 << 62);
-      o1 >>= 2;
-      orr >>= 1;
-    }
-    const int src = (int)(((uint32_t)lane - r * R) * G) & 63;
-    const uint32_t rt = __shfl(res_t, src);
-    const uint32_t rv = __shfl(res_s, src);
-    if ((uint32_t)lane >= r * R && (uint32_t)lane < r * R + R) {
-      my_t = rt;
-      my_s = rv;
-    }
-  }
-  out_t = my_t;
-  out_s = my_s;
-  if (!valid) return;
-  if (my_t == NONCONV) {
-    const uint32_t slot = atomicAdd(a.nc_count, 1u);
-    a.nc_chunk[slot] = (uint32_t)c;
-    a.nc_slot[c] = slot;
-  }
-  a.conv_t[c] = my_t;
-  a.conv_s[c] = my_s;
-}
-
-// Speculation, then the scan of each chunk from its converging point (one
-// lane per chunk), then the join inside the wave: the predecessor lane's
-// last state is this chunk's true first state, from which the prefix before
-// the converging point is recounted.  Each wave first runs the speculation
-// of its own 64 chunks (the tile), with the one-symbol table and the PSS
-// table in LDS.  The first lane of a wave, non-converged chunks and their
-// successors are left to the fix-up kernel.
-// HIST: per-final-state visit histogram in LDS (several patterns); else a
-// total with exact two-symbol counts.
-template <int ENC, int SHIFT, int STEP, bool HIST>
-__global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(COEX_TAIL_WAVES, 8))) void k_tail(ScanArgs a) {
-  extern __shared__ __align__(16) char lds[];
-  if (STEP == 2) copy_to_lds(lds, a.T2, a.n_states * 64u);
-  copy_to_lds(lds + a.lds_t1_off, a.T1, a.n_states * 16u);
-  uint32_t* wl = reinterpret_cast<uint32_t*>(lds + a.lds_w_off);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + a.lds_hist_off);
-  for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x) {
-    wl[i] = a.wtab[i];
-    if (HIST) hist[i] = 0;
-  }
-  const uint32_t* pss_off = a.pss_off;
-  const uint16_t* pss_states = a.pss_states;
-  if (a.spec_pss_off) {
-    uint32_t* po = reinterpret_cast<uint32_t*>(lds + a.spec_pss_off);
-    uint16_t* ps = reinterpret_cast<uint16_t*>(lds + a.spec_pss_states);
-    for (uint32_t i = threadIdx.x; i < a.pss_n_off; i += blockDim.x) po[i] = a.pss_off[i];
-    for (uint32_t i = threadIdx.x; i < a.pss_n_states; i += blockDim.x) ps[i] = a.pss_states[i];
-    pss_off = po;
-    pss_states = ps;
-  }
-  __syncthreads();
-  const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
-  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
-  using Sink = typename std::conditional<HIST, SinkHist, SinkTotal>::type;
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = c < a.n_chunks;
-  uint32_t my_t = NONCONV, my_s = 0;
-  if ((c >> 6) < a.n_tiles) spec_tile<ENC, SHIFT>(a, Tab{nullptr, tb.t1, a.q0s}, pss_off, pss_states, c >> 6, my_t, my_s);
-  if (!valid) my_t = NONCONV;
-  const bool conv = my_t != NONCONV;
-  const uint64_t lo = c * a.chunk;
-  uint32_t out_e = 0, out_cnt = 0;
-  if (conv) {
-    const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-    Sink sink;
-    if constexpr (HIST) sink = SinkHist{wl, hist};
-    else sink = SinkTotal{wl};
-    out_e = scan_range<ENC, SHIFT, STEP>(a, tb, my_s, lo + my_t, hi, sink);
-    out_cnt = sink.cnt;
-  }
-  const uint32_t pe = __shfl_up(out_e, 1u);
-  const int pconv = __shfl_up((int)conv, 1u);
-  uint64_t fixed_total = 0;
-  bool fixed = false;
-  if (conv && lane > 0 && pconv) {
-    const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-    Sink sink;
-    if constexpr (HIST) sink = SinkHist{wl, hist};
-    else sink = SinkTotal{wl};
-    uint64_t sy0, sy1, rs;
-    if ((lo & 63) == 0 && lo + SPEC_WIN <= a.n) front_symbols<ENC>(a, lo, sy0, sy1, rs);
-    else stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
-    const uint32_t e = run_staged<SHIFT>(tb, pe, sy0, sy1, rs, my_t, lo, sink);
-    if (e != my_s) atomicOr(a.err, 32u);
-    out_cnt += sink.cnt;
-    fixed = true;
-    fixed_total = out_cnt;
-  }
-  if (valid) {
-    // the first chunk of every tile goes to the fix-up kernel without a list
-    // entry (its symbols before the converging point are kept for it); the
-    // others only when their join could not be done here
-    if (!fixed && lane > 0) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)c;
-    else if (fixed && a.chunk_cnt) a.chunk_cnt[c] = out_cnt;
-    if (lane == 0 && conv) {
-      uint64_t sy0, sy1, rs;
-      const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-      if ((lo & 63) == 0 && lo + SPEC_WIN <= a.n) front_symbols<ENC>(a, lo, sy0, sy1, rs);
-      else stage_symbols<ENC>(a, lo, hi, sy0, sy1, rs);
-      uint64_t* f = a.front + 3 * (c / TILE);
-      f[0] = sy0;
-      f[1] = sy1;
-      f[2] = rs;
-    }
-    if (fixed) a.conv_t[c] = my_t | FIXED;
-    a.end_s[c] = out_e;
-    a.tail_cnt[c] = out_cnt;
-  }
-  if constexpr (HIST) {
-    // per-pattern counts: each final state's visits, added to the patterns it ends
-    __syncthreads();
-    if (a.pat_counts)
-      for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x)
-        if (hist[i])
-          for (uint32_t j = a.acc_out_off[i]; j < a.acc_out_off[i + 1]; ++j)
-            atomicAdd(a.pat_counts + a.acc_out_ids[j], (unsigned long long)hist[i]);
-  } else {
-    // one atomic per block for the joined chunks' total
-    for (int o = 32; o > 0; o >>= 1) fixed_total += __shfl_down(fixed_total, o);
-    uint64_t* red = reinterpret_cast<uint64_t*>(lds + a.lds_red_off);
-    if (lane == 0) red[threadIdx.x >> 6] = fixed_total;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t t = 0;
-      for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) t += red[w];
-      if (t) atomicAdd(a.total, (unsigned long long)t);
-    }
-  }
 }
 
 // Non-converged chunks: one wave per chunk, one lane per candidate, each run
@@ -540,6 +282,7 @@ struct DeviceCopy {
   bool t2_exact = true;
   // per encoding [0] = byte, [1] = 2-bit
   const uint32_t* T2[2] = {nullptr, nullptr};
+  const uint16_t* T3[2] = {nullptr, nullptr};  // automata of at most kMaxStatesStep3 states
   const uint32_t* T1[2] = {nullptr, nullptr};
   const uint32_t* wtab = nullptr;
   const uint32_t* acc_out_off = nullptr;
@@ -610,6 +353,8 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
   auto weight = [&](uint32_t s) -> uint32_t { return d.out_off[s + 1] - d.out_off[s]; };
   // host images
   std::vector<uint32_t> T1[2], T2[2];
+  std::vector<uint16_t> T3[2];
+  const bool has_t3 = S == 6 && n <= kMaxStatesStep3;
   for (int e = 0; e < 2; ++e) {
     const int* ord = e == 1 ? kOrd2bit : kOrdByte;
     T1[e].resize((size_t)n * 4);
@@ -629,6 +374,20 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
           T2[e][s * 16 + g] = (s2 << 6) | (cnt << 24);
         }
     }
+    if (has_t3) {
+      // three symbols per entry: succ3 * 64 | (an accepting state among the
+      // three visited); row n repeats row 0
+      T3[e].resize((size_t)(n + 1) * 64);
+      for (uint32_t s = 0; s < n; ++s)
+        for (int g = 0; g < 64; ++g) {
+          const uint32_t s1 = d.delta[s * 4 + ord[g & 3]];
+          const uint32_t s2 = d.delta[s1 * 4 + ord[(g >> 2) & 3]];
+          const uint32_t s3 = d.delta[s2 * 4 + ord[g >> 4]];
+          const bool hit = d.acc_index[s1] >= 0 || d.acc_index[s2] >= 0 || d.acc_index[s3] >= 0;
+          T3[e][(size_t)s * 64 + g] = (uint16_t)((s3 << 6) | (hit ? 1u : 0u));
+        }
+      std::copy(T3[e].begin(), T3[e].begin() + 64, T3[e].begin() + (size_t)n * 64);
+    }
   }
   std::vector<uint32_t> aoff(d.n_accepting + 1, 0), aids;
   for (uint32_t i = 0; i < d.n_accepting; ++i) {
@@ -645,9 +404,10 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
     off = align_up(off + std::max<size_t>(bytes, 16), 256);
     return parts.size() - 1;
   };
-  size_t iT2[2] = {0, 0}, iT1[2];
+  size_t iT2[2] = {0, 0}, iT3[2] = {0, 0}, iT1[2];
   for (int e = 0; e < 2; ++e) {
     if (S == 6) iT2[e] = add(T2[e].data(), T2[e].size() * 4);
+    if (has_t3) iT3[e] = add(T3[e].data(), T3[e].size() * 2);
     iT1[e] = add(T1[e].data(), T1[e].size() * 4);
   }
   size_t iw = add(w.data(), w.size() * 4);
@@ -667,6 +427,7 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
   auto at = [&](size_t i) { return dc->buf + parts[i].off; };
   for (int e = 0; e < 2; ++e) {
     dc->T2[e] = S == 6 ? reinterpret_cast<const uint32_t*>(at(iT2[e])) : nullptr;
+    dc->T3[e] = has_t3 ? reinterpret_cast<const uint16_t*>(at(iT3[e])) : nullptr;
     dc->T1[e] = reinterpret_cast<const uint32_t*>(at(iT1[e]));
   }
   dc->wtab = reinterpret_cast<const uint32_t*>(at(iw));
@@ -729,7 +490,7 @@ int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) 
 }
 
 struct Plan {
-  uint32_t shift, step, k, group, max_cand, blocks, lds_bytes;
+  uint32_t shift, step, chains, block, k, group, max_cand, blocks, lds_bytes;
   bool all_conv;  // every chunk's candidates must agree inside the window (synchronising depth)
   bool direct;    // counts only and all_conv: no non-converged maps, no join kernels
   uint64_t chunk, n_chunks, n_tiles;
@@ -746,42 +507,30 @@ uint32_t pss_lds_bytes(const Dfa& d, uint32_t k) {
   return b <= kPssLdsMax ? b : 0u;
 }
 
+// Per-wave partial sums of the chunk-scan kernel (up to 16 waves per block).
+constexpr uint32_t kTailRedBytes = 16 * 8;
+
+// LDS bytes in front of the one-symbol table: the multi-symbol table.
+uint32_t wide_table_bytes(uint32_t step, uint32_t n) { return step == 2 ? n * 64 : step == 3 ? (n + 1) * 128 : 0; }
+
 uint32_t tail_lds_bytes(uint32_t step, const Dfa& d, uint32_t k) {
   const uint32_t n = d.n_states;
   const uint32_t acc = (uint32_t)align_up(d.n_accepting * 4, 16);
-  return (step == 2 ? n * 64 : 0) + n * 16 + 2 * acc + pss_lds_bytes(d, k) + (kScanBlock / 64) * 8 + 16;
+  return wide_table_bytes(step, n) + n * 16 + 2 * acc + pss_lds_bytes(d, k) + kTailRedBytes + 16;
 }
 
-template <int ENC, int SHIFT, int STEP, bool HIST>
-int occupancy_of(uint32_t lds) {
-  int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_tail<ENC, SHIFT, STEP, HIST>, kScanBlock, lds) !=
-      hipSuccess)
-    return 1;
-  return std::max(1, blocks);
-}
+TailKey tail_key(const Plan& P) { return TailKey{P.enc, (int)P.shift, (int)P.step, (int)P.chains, P.hist}; }
 
 // Resident blocks per CU of the chunk-scan kernel the plan will launch.
 uint32_t tail_blocks_per_cu(const Plan& P, const Dfa& d) {
   static std::mutex mu;
-  static std::map<std::tuple<int, uint32_t, uint32_t, bool, uint32_t>, int> cache;
+  static std::map<std::tuple<int, uint32_t, uint32_t, uint32_t, bool, uint32_t>, int> cache;
   const uint32_t lds = tail_lds_bytes(P.step, d, P.k);
-  const auto key = std::make_tuple(P.enc, P.shift, P.step, P.hist, lds);
+  const auto key = std::make_tuple(P.enc, P.shift, P.step, P.chains, P.hist, lds);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return (uint32_t)it->second;
-  int b = 1;
-  const bool by = P.enc == 0;
-  if (P.shift == 6 && P.step == 2) {
-    if (by) b = P.hist ? occupancy_of<ENC_BYTE, 6, 2, true>(lds) : occupancy_of<ENC_BYTE, 6, 2, false>(lds);
-    else b = P.hist ? occupancy_of<ENC_2BIT, 6, 2, true>(lds) : occupancy_of<ENC_2BIT, 6, 2, false>(lds);
-  } else if (P.shift == 6) {
-    if (by) b = P.hist ? occupancy_of<ENC_BYTE, 6, 1, true>(lds) : occupancy_of<ENC_BYTE, 6, 1, false>(lds);
-    else b = P.hist ? occupancy_of<ENC_2BIT, 6, 1, true>(lds) : occupancy_of<ENC_2BIT, 6, 1, false>(lds);
-  } else {
-    if (by) b = P.hist ? occupancy_of<ENC_BYTE, 4, 1, true>(lds) : occupancy_of<ENC_BYTE, 4, 1, false>(lds);
-    else b = P.hist ? occupancy_of<ENC_2BIT, 4, 1, true>(lds) : occupancy_of<ENC_2BIT, 4, 1, false>(lds);
-  }
+  const int b = std::max(1, tail_occupancy(tail_key(P), lds));
   cache[key] = b;
   return (uint32_t)b;
 }
@@ -790,9 +539,16 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
               bool force_hist) {
   P.enc = sq.encoding == COEX_ENC_2BIT ? 1 : 0;
   P.shift = dc.shift;
-  if (o && o->step > 2) return COEX_EINVAL;
-  P.step = (o && o->step) ? o->step : (dc.shift == 6 ? 2u : 1u);
+  if (o && o->step > 3) return COEX_EINVAL;
+  // default: three symbols per lookup for 2-bit input when the automaton has
+  // a three-symbol table (fewest dependent LDS reads per base), else two
+  const uint32_t dstep = dc.shift != 6 ? 1u : (P.enc == 1 && dc.T3[0] ? 3u : 2u);
+  P.step = (o && o->step) ? o->step : dstep;
   if (P.step == 2 && dc.shift != 6) return COEX_EUNSUPPORTED;
+  if (P.step == 3 && !dc.T3[0]) return COEX_EUNSUPPORTED;
+  if (o && o->chains > 2) return COEX_EINVAL;
+  P.chains = (o && o->chains) ? o->chains : 1u;
+  if (P.chains == 2 && P.step == 1) return COEX_EUNSUPPORTED;
   // lookback
   if (o && o->lookback) {
     if (o->lookback > kMaxLookback) return COEX_EINVAL;
@@ -817,13 +573,14 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
   }
   const uint64_t n = sq.n_bases;
   P.hist = force_hist || d.n_patterns > 1 || (P.step == 2 && !dc.t2_exact);
+  P.block = (uint32_t)tail_block(tail_key(P));
   if (o && o->chunk) {
     P.chunk = o->chunk;
   } else {
     // one round of the chunk-scan kernel over the whole GPU: as many chunks
     // as lanes that can be resident at once (occupancy of the actual kernel
     // with its LDS), chunk length a multiple of 512 bases
-    const uint64_t lanes = (uint64_t)n_cu * tail_blocks_per_cu(P, d) * kScanBlock;
+    const uint64_t lanes = (uint64_t)n_cu * tail_blocks_per_cu(P, d) * P.block * P.chains;
     uint64_t c = (n + lanes - 1) / std::max<uint64_t>(1, lanes);
     c = std::max<uint64_t>(512, align_up(c, 512));
     // bound the non-converged scratch (chunks * candidates * 8 bytes) to 512 MiB
@@ -844,6 +601,23 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
   return COEX_OK;
 }
 
+}  // namespace
+
+int tail_block(const TailKey& k) { return (k.step == 3 && k.chains == 1) ? 1024 : kScanBlock; }
+
+int tail_occupancy(const TailKey& k, uint32_t lds) {
+  if (k.enc == ENC_BYTE) return k.hist ? tail_occupancy_byte_hist(k, lds) : tail_occupancy_byte_count(k, lds);
+  return k.hist ? tail_occupancy_2bit_hist(k, lds) : tail_occupancy_2bit_count(k, lds);
+}
+
+bool tail_launch(const TailKey& k, uint32_t blocks, uint32_t lds, hipStream_t st, const ScanArgs& a) {
+  if (k.enc == ENC_BYTE)
+    return k.hist ? tail_launch_byte_hist(k, blocks, lds, st, a) : tail_launch_byte_count(k, blocks, lds, st, a);
+  return k.hist ? tail_launch_2bit_hist(k, blocks, lds, st, a) : tail_launch_2bit_count(k, blocks, lds, st, a);
+}
+
+namespace {
+
 // Events bracketing the scan kernel when the call asked for timing.
 std::pair<hipEvent_t, hipEvent_t>* timing_slot(Workspace* w) {
   if (!w || w->ev_used >= kMaxTimedLaunches) return nullptr;
@@ -856,20 +630,17 @@ std::pair<hipEvent_t, hipEvent_t>* timing_slot(Workspace* w) {
   return &w->ev[w->ev_used++];
 }
 
-template <int ENC, int SHIFT, int STEP, bool HIST>
-void launch_scan(const Plan& P, const ScanArgs& a, int n_cu, hipStream_t st, Workspace* timed) {
-  (void)n_cu;
-  // speculation and scan: one lane per chunk, one tile of 64 chunks per wave
-  auto kt = k_tail<ENC, SHIFT, STEP, HIST>;
-  (void)hipFuncSetAttribute((const void*)kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
-  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (P.n_chunks + kScanBlock - 1) / kScanBlock);
+void launch_scan(const Plan& P, const ScanArgs& a, hipStream_t st, Workspace* timed) {
+  // speculation and scan: one lane per chunk and chain, CH tiles of 64 chunks per wave
+  const uint64_t tiles_per_block = (uint64_t)(P.block / 64) * P.chains;
+  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (P.n_tiles + tiles_per_block - 1) / tiles_per_block);
   auto* ev = timed ? timing_slot(timed) : nullptr;
   if (ev) (void)hipEventRecord(ev->first, st);
-  hipLaunchKernelGGL(kt, dim3(blocks), dim3(kScanBlock), P.lds_bytes, st, a);
+  (void)tail_launch(tail_key(P), blocks, P.lds_bytes, st, a);
   if (ev) (void)hipEventRecord(ev->second, st);
 }
 
-template <int ENC, int SHIFT, int STEP>
+template <int ENC, int SHIFT>
 void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint64_t* counts, bool emit_counts,
                      Workspace* timed) {
   // counts go straight to the caller's buffer (zeroed here): per pattern from
@@ -878,8 +649,7 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
   if (emit_counts && !P.hist && a.n_patterns > 0) a.total = reinterpret_cast<unsigned long long*>(counts);
   hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, a, counts, emit_counts ? a.n_patterns : 0u);
   if (P.n_chunks == 0) return;
-  if (P.hist) launch_scan<ENC, SHIFT, STEP, true>(P, a, n_cu, st, timed);
-  else launch_scan<ENC, SHIFT, STEP, false>(P, a, n_cu, st, timed);
+  launch_scan(P, a, st, timed);
   constexpr int DSTEP = 1;  // non-converged runs and prefix recounts: one-symbol table staged in LDS
   // counts of an automaton that synchronises inside every chunk's window need
   // neither non-converged maps nor the true first state of every chunk (the
@@ -937,7 +707,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   if (P.chunk > (0xFFFFFFFFull / std::max<uint32_t>(1, 2 * d.max_out + 1))) return COEX_EINVAL;
   const uint32_t S = P.shift;
   const uint32_t n = d.n_states;
-  const uint32_t t1_off = P.step == 2 ? n * 64 : 0;
+  const uint32_t t1_off = wide_table_bytes(P.step, n);
   const uint32_t w_off = t1_off + n * 16;
   const uint32_t h_off = w_off + (uint32_t)align_up(d.n_accepting * 4, 16);
   uint32_t lds_end = h_off + (uint32_t)align_up(d.n_accepting * 4, 16);
@@ -952,7 +722,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
     lds_end += pss_lds_bytes(d, P.k);
   }
   a_red_off_tmp = lds_end;  // per-wave partial sums of the scan kernel
-  lds_end += (kScanBlock / 64) * 8;
+  lds_end += kTailRedBytes;
   P.lds_bytes = lds_end + 16;
   // workspace layout
   const uint64_t nc = P.n_chunks;
@@ -988,6 +758,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.n_tiles = P.n_tiles;
   const int e = P.enc;
   a.T2 = C.dc->T2[e];
+  a.T3 = C.dc->T3[e];
   a.T1 = C.dc->T1[e];
   a.wtab = C.dc->wtab;
   a.n_states = n;
@@ -1036,15 +807,13 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
 void run_pipeline(Call& C, uint64_t* counts, bool emit_counts) {
   const bool b = C.P.enc == 0;
   const Plan& P = C.P;
-  if (P.shift == 6 && P.step == 2) {
-    if (b) launch_pipeline<ENC_BYTE, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
-    else launch_pipeline<ENC_2BIT, 6, 2>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
-  } else if (P.shift == 6) {
-    if (b) launch_pipeline<ENC_BYTE, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
-    else launch_pipeline<ENC_2BIT, 6, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
+  Workspace* t = C.timed ? C.wsp : nullptr;
+  if (P.shift == 6) {
+    if (b) launch_pipeline<ENC_BYTE, 6>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
+    else launch_pipeline<ENC_2BIT, 6>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
   } else {
-    if (b) launch_pipeline<ENC_BYTE, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
-    else launch_pipeline<ENC_2BIT, 4, 1>(P, C.a, C.n_cu, C.st, counts, emit_counts, C.timed ? C.wsp : nullptr);
+    if (b) launch_pipeline<ENC_BYTE, 4>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
+    else launch_pipeline<ENC_2BIT, 4>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
   }
 }
 

@@ -15,6 +15,7 @@ namespace coex {
 
 constexpr uint32_t kMaxStates = 4096;      // device tables index rows with 16-bit byte offsets
 constexpr uint32_t kMaxStatesStep2 = 1024; // two-symbol table rows are 64 B
+constexpr uint32_t kMaxStatesStep3 = 1023; // three-symbol entries hold row * 64 + flag in 16 bits
 constexpr uint32_t kMaxLookback = 8;
 constexpr uint32_t kNoSync = 0xFFFFFFFFu;
 

@@ -25,6 +25,13 @@
 //                     g = c0 | c1 << 2 for symbols c0 then c1; count = number
 //                     of pattern ends at the two visited states (or just 1 if
 //                     any, when counts could overflow the 8-bit field).
+//   T3 (three symbols, at most 1023 states): u16[n + 1][64] = succ3 << 6 |
+//                     flag, column g = c0 | c1 << 2 | c2 << 4; flag = an
+//                     accepting state is among the three visited ones.  The
+//                     entry is the next state register value itself (flag in
+//                     bit 0, which no row offset uses); row n repeats row 0,
+//                     so a walk that carries a set flag into the next address
+//                     still reads table entries (the word is replayed anyway).
 //   Column order is the encoding's natural one: A,C,G,T for 2-bit codes and
 //   A,C,T,G for bytes ((byte >> 1) & 3).
 #pragma once
@@ -56,6 +63,7 @@ struct ScanArgs {
   uint64_t n_tiles;
   // tables (global copies)
   const uint32_t* T2;
+  const uint16_t* T3;
   const uint32_t* T1;
   const uint32_t* wtab;       // weight (number of patterns) per accepting index
   uint32_t n_states;
@@ -184,6 +192,7 @@ __device__ __forceinline__ uint32_t t2_lookup(const Tab& tb, uint32_t s, uint32_
 // the sink does not need per-position detail (kReplay == false).
 struct SinkTotal {      // total weighted count from exact two-symbol counts
   static constexpr bool kReplay = false;
+  static constexpr bool kOutline = false;
   const uint32_t* w;    // weight per accepting index
   uint32_t cnt = 0;
   __device__ void word(uint32_t c) { cnt += c; }
@@ -192,6 +201,7 @@ struct SinkTotal {      // total weighted count from exact two-symbol counts
 
 struct SinkHist {       // per accepting state visits in an LDS histogram
   static constexpr bool kReplay = true;
+  static constexpr bool kOutline = false;
   const uint32_t* w;
   uint32_t* hist;
   uint32_t cnt = 0;
@@ -204,6 +214,7 @@ struct SinkHist {       // per accepting state visits in an LDS histogram
 
 struct SinkGlobal {     // weighted count, and per-pattern counts straight to global memory
   static constexpr bool kReplay = true;
+  static constexpr bool kOutline = false;
   const uint32_t* w;
   const uint32_t* out_off;     // per accepting index: its pattern ids
   const uint32_t* out_ids;
@@ -219,6 +230,7 @@ struct SinkGlobal {     // weighted count, and per-pattern counts straight to gl
 
 struct SinkPositions {  // end positions and pattern ids, in order
   static constexpr bool kReplay = true;
+  static constexpr bool kOutline = false;
   const uint32_t* out_off;   // per accepting index
   const uint32_t* out_ids;
   int64_t* pos;
@@ -241,6 +253,7 @@ struct SinkPositions {  // end positions and pattern ids, in order
 
 struct SinkRecord {     // per chunk, per pattern counts
   static constexpr bool kReplay = true;
+  static constexpr bool kOutline = false;
   const uint32_t* out_off;
   const uint32_t* out_ids;
   uint64_t* row;
@@ -279,12 +292,23 @@ __device__ __forceinline__ uint32_t word_slow(const Tab& tb, uint32_t s, uint32_
   return s;
 }
 
+// A word one base at a time through the sink's own out-of-line routine when
+// it has one (kOutline: keeps the rare path out of the unrolled hot loop).
+template <int SHIFT, class Sink>
+__device__ __forceinline__ uint32_t slow_word(const Tab& tb, uint32_t s, uint32_t cols, uint32_t rst, uint32_t act,
+                                              uint64_t p, Sink& sink) {
+  if constexpr (Sink::kOutline) return sink.template slow<SHIFT>(s, cols, rst, act);
+  else return word_slow<SHIFT>(tb, s, cols, rst, act, p, sink);
+}
+
 // LDS read at a byte address.  The two-symbol table is staged at LDS
 // address 0 (the kernels using it declare no other LDS), so a state value
 // (row byte offset) plus a column offset is a complete LDS address.
 typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 typedef __attribute__((address_space(3))) const char lds_c;
 __device__ __forceinline__ uint32_t lds_at(uint32_t addr) { return *(lds_u32*)(uintptr_t)addr; }
+typedef __attribute__((address_space(3))) const uint16_t lds_u16;
+__device__ __forceinline__ uint32_t lds_u16_at(uint32_t addr) { return *(lds_u16*)(uintptr_t)addr; }
 
 // (e & 0xFFFF) + byte B of x in one VALU instruction (sub-dword operand
 // selection): the next row offset from a table entry plus a column offset.
@@ -307,16 +331,29 @@ __device__ __forceinline__ uint32_t row_plus_byte(uint32_t e, uint32_t x) {
 }
 
 // 16 symbols without resets: eight two-symbol lookups (STEP 2, table in LDS
-// at address 0) or sixteen one-symbol lookups.  Returns the state after the
-// word; `c` receives the number of pattern ends in the word (STEP 2, exact
-// two-symbol counts) or a nonzero flag when any accepting state was visited.
+// at address 0), five three-symbol lookups and one one-symbol lookup (STEP 3,
+// three-symbol table at LDS address 0), or sixteen one-symbol lookups.
+// Returns the state after the word; `c` receives the number of pattern ends
+// in the word (STEP 2, exact two-symbol counts) or a nonzero flag when any
+// accepting state was visited (STEP 3: the returned state is then not
+// meaningful and the caller replays the word).
 // For STEP 2 the two-bit columns are spread into byte lanes once per word
 // (columns of even grams times 4 in xa, odd grams in xb), so each lookup
 // costs one address instruction.
 template <int SHIFT, int STEP>
 __device__ __forceinline__ uint32_t walk16(const Tab& tb, uint32_t s, uint32_t cols, uint32_t& c) {
-  static_assert(STEP == 1 || SHIFT == 6, "two-symbol tables need 64-byte rows");
-  if constexpr (STEP == 2) {
+  static_assert(STEP == 1 || SHIFT == 6, "two- and three-symbol tables need 64-byte state units");
+  if constexpr (STEP == 3) {
+    // entry = next state register (row * 64) | flag; address = 2 * (entry + column)
+    const uint32_t e0 = lds_u16_at((s + (cols & 63u)) << 1);
+    const uint32_t e1 = lds_u16_at((e0 + ((cols >> 6) & 63u)) << 1);
+    const uint32_t e2 = lds_u16_at((e1 + ((cols >> 12) & 63u)) << 1);
+    const uint32_t e3 = lds_u16_at((e2 + ((cols >> 18) & 63u)) << 1);
+    const uint32_t e4 = lds_u16_at((e3 + ((cols >> 24) & 63u)) << 1);
+    const uint32_t t = t1_lookup<SHIFT>(tb, e4, cols >> 30);  // e4 >> 2 drops the flag bit
+    c = ((e0 | e1 | e2 | e3 | e4) & 1u) | (t >> 16);
+    return t & 0xFFFFu;
+  } else if constexpr (STEP == 2) {
     const uint32_t xa = (cols << 2) & 0x3C3C3C3Cu;
     const uint32_t xb = (cols >> 2) & 0x3C3C3C3Cu;
     const uint32_t e0 = lds_at(row_plus_byte<0>(s, xa));
@@ -342,30 +379,100 @@ __device__ __forceinline__ uint32_t walk16(const Tab& tb, uint32_t s, uint32_t c
   }
 }
 
+// What follows the table walk of a word without a reset boundary (rst is 0
+// or all ones): a word inside an N run ends in q0 and reports nothing; a word
+// with matches is replayed base by base when the sink needs the detail, when
+// the step cannot count exactly (STEP 1) or when the walk's end state is not
+// meaningful (STEP 3 with a flag).
+template <int SHIFT, int STEP, class Sink>
+__device__ __forceinline__ uint32_t finish_word(const Tab& tb, uint32_t s, uint32_t e, uint32_t c, uint32_t cols,
+                                                uint32_t rst, uint64_t p, Sink& sink) {
+  if (rst) {
+    e = tb.q0s;
+    c = 0;
+  }
+  if constexpr (STEP == 3) {
+    if (__builtin_expect(c != 0u, 0)) e = slow_word<SHIFT>(tb, s, cols, 0u, 0xFFFFu, p, sink);
+  } else if constexpr (Sink::kReplay || STEP == 1) {
+    if (__builtin_expect(c != 0u, 0)) slow_word<SHIFT>(tb, s, cols, 0u, 0xFFFFu, p, sink);
+  } else {
+    sink.word(c);
+  }
+  return e;
+}
+
 // One 16-base word with reset bits `rst`.  Words without resets and words
 // made only of resets (inside runs of N) take the table walk; the latter
 // end in q0 and report nothing, so lanes inside N runs do not diverge from
-// the others.  Words with a reset boundary go one base at a time.  A word
-// with matches is replayed base by base when the sink needs the detail (or
-// when the step cannot count exactly).
+// the others.  Words with a reset boundary go one base at a time.
 template <int SHIFT, int STEP, class Sink>
 __device__ __forceinline__ uint32_t run_word(const Tab& tb, uint32_t s, uint32_t cols, uint32_t rst, uint64_t p,
                                              Sink& sink) {
   if (rst == 0u || rst == 0xFFFFu) {
     uint32_t c;
-    uint32_t e = walk16<SHIFT, STEP>(tb, s, cols, c);
-    if (rst) {
-      e = tb.q0s;
-      c = 0;
-    }
-    if constexpr (Sink::kReplay || STEP == 1) {
-      if (c) word_slow<SHIFT>(tb, s, cols, 0u, 0xFFFFu, p, sink);
-    } else {
-      sink.word(c);
-    }
-    return e;
+    const uint32_t e = walk16<SHIFT, STEP>(tb, s, cols, c);
+    return finish_word<SHIFT, STEP>(tb, s, e, c, cols, rst, p, sink);
   }
-  return word_slow<SHIFT>(tb, s, cols, rst, 0xFFFFu, p, sink);
+  return slow_word<SHIFT>(tb, s, cols, rst, 0xFFFFu, p, sink);
+}
+
+// Two independent words (two chunks of one lane) walked with their lookups
+// interleaved, so two dependent chains of LDS reads are in flight per lane.
+template <int SHIFT, int STEP>
+__device__ __forceinline__ void walk16x2(const Tab& tb, uint32_t s0, uint32_t cols0, uint32_t& e0, uint32_t& c0,
+                                         uint32_t s1, uint32_t cols1, uint32_t& e1, uint32_t& c1) {
+  if constexpr (STEP == 3) {
+    const uint32_t a0 = lds_u16_at((s0 + (cols0 & 63u)) << 1);
+    const uint32_t b0 = lds_u16_at((s1 + (cols1 & 63u)) << 1);
+    const uint32_t a1 = lds_u16_at((a0 + ((cols0 >> 6) & 63u)) << 1);
+    const uint32_t b1 = lds_u16_at((b0 + ((cols1 >> 6) & 63u)) << 1);
+    const uint32_t a2 = lds_u16_at((a1 + ((cols0 >> 12) & 63u)) << 1);
+    const uint32_t b2 = lds_u16_at((b1 + ((cols1 >> 12) & 63u)) << 1);
+    const uint32_t a3 = lds_u16_at((a2 + ((cols0 >> 18) & 63u)) << 1);
+    const uint32_t b3 = lds_u16_at((b2 + ((cols1 >> 18) & 63u)) << 1);
+    const uint32_t a4 = lds_u16_at((a3 + ((cols0 >> 24) & 63u)) << 1);
+    const uint32_t b4 = lds_u16_at((b3 + ((cols1 >> 24) & 63u)) << 1);
+    const uint32_t ta = t1_lookup<SHIFT>(tb, a4, cols0 >> 30);
+    const uint32_t tb1 = t1_lookup<SHIFT>(tb, b4, cols1 >> 30);
+    c0 = ((a0 | a1 | a2 | a3 | a4) & 1u) | (ta >> 16);
+    c1 = ((b0 | b1 | b2 | b3 | b4) & 1u) | (tb1 >> 16);
+    e0 = ta & 0xFFFFu;
+    e1 = tb1 & 0xFFFFu;
+  } else if constexpr (STEP == 2) {
+    const uint32_t xa = (cols0 << 2) & 0x3C3C3C3Cu, xb = (cols0 >> 2) & 0x3C3C3C3Cu;
+    const uint32_t ya = (cols1 << 2) & 0x3C3C3C3Cu, yb = (cols1 >> 2) & 0x3C3C3C3Cu;
+    const uint32_t a0 = lds_at(row_plus_byte<0>(s0, xa)), b0 = lds_at(row_plus_byte<0>(s1, ya));
+    const uint32_t a1 = lds_at(row_plus_byte<0>(a0, xb)), b1 = lds_at(row_plus_byte<0>(b0, yb));
+    const uint32_t a2 = lds_at(row_plus_byte<1>(a1, xa)), b2 = lds_at(row_plus_byte<1>(b1, ya));
+    const uint32_t a3 = lds_at(row_plus_byte<1>(a2, xb)), b3 = lds_at(row_plus_byte<1>(b2, yb));
+    const uint32_t a4 = lds_at(row_plus_byte<2>(a3, xa)), b4 = lds_at(row_plus_byte<2>(b3, ya));
+    const uint32_t a5 = lds_at(row_plus_byte<2>(a4, xb)), b5 = lds_at(row_plus_byte<2>(b4, yb));
+    const uint32_t a6 = lds_at(row_plus_byte<3>(a5, xa)), b6 = lds_at(row_plus_byte<3>(b5, ya));
+    const uint32_t a7 = lds_at(row_plus_byte<3>(a6, xb)), b7 = lds_at(row_plus_byte<3>(b6, yb));
+    c0 = (a0 + a1 + a2 + a3 + a4 + a5 + a6 + a7) >> 24;
+    c1 = (b0 + b1 + b2 + b3 + b4 + b5 + b6 + b7) >> 24;
+    e0 = a7 & 0xFFFFu;
+    e1 = b7 & 0xFFFFu;
+  } else {
+    e0 = walk16<SHIFT, STEP>(tb, s0, cols0, c0);
+    e1 = walk16<SHIFT, STEP>(tb, s1, cols1, c1);
+  }
+}
+
+// One word of each of two chains.
+template <int SHIFT, int STEP, class Sink>
+__device__ __forceinline__ void run_word2(const Tab& tb, uint32_t& s0, uint32_t cols0, uint32_t rst0, uint64_t p0,
+                                          Sink& k0, uint32_t& s1, uint32_t cols1, uint32_t rst1, uint64_t p1,
+                                          Sink& k1) {
+  if ((rst0 == 0u || rst0 == 0xFFFFu) && (rst1 == 0u || rst1 == 0xFFFFu)) {
+    uint32_t e0, c0, e1, c1;
+    walk16x2<SHIFT, STEP>(tb, s0, cols0, e0, c0, s1, cols1, e1, c1);
+    s0 = finish_word<SHIFT, STEP>(tb, s0, e0, c0, cols0, rst0, p0, k0);
+    s1 = finish_word<SHIFT, STEP>(tb, s1, e1, c1, cols1, rst1, p1, k1);
+  } else {
+    s0 = run_word<SHIFT, STEP>(tb, s0, cols0, rst0, p0, k0);
+    s1 = run_word<SHIFT, STEP>(tb, s1, cols1, rst1, p1, k1);
+  }
 }
 
 // A block of sequence held in registers: 512 bases (128 bytes of 2-bit codes
@@ -486,14 +593,69 @@ __device__ __forceinline__ void load_block(const ScanArgs& a, uint64_t base, Blo
   else b.load_partial(a, base);
 }
 
-// Runs the words of block `b` (first base `base`) that hold bases in
-// [lo, hi).  CHECKED = false promises the whole block lies in [lo, hi).
-template <int ENC, int SHIFT, int STEP, bool CHECKED, class Sink>
-__device__ __forceinline__ uint32_t run_block(const Tab& tb, uint32_t s, const Block<ENC>& b, uint64_t base,
-                                              uint64_t lo, uint64_t hi, Sink& sink) {
-  constexpr int W = Block<ENC>::WORDS;
+// 48 symbols (three words, no resets) as sixteen three-symbol lookups: the
+// triples run across the word boundaries (bits 6j..6j+5 of w0 | w1 << 32 |
+// w2 << 64).  Returns the state after the unit; `c` is nonzero when an
+// accepting state was visited (the state is then not meaningful and the unit
+// is replayed).
+__device__ __forceinline__ uint32_t walk48(uint32_t s, uint32_t w0, uint32_t w1, uint32_t w2, uint32_t& c) {
+  uint32_t g[16];
 #pragma unroll
-  for (int w = 0; w < W; ++w) {
+  for (int j = 0; j < 5; ++j) g[j] = (w0 >> (6 * j)) & 63u;
+  g[5] = __builtin_amdgcn_alignbit(w1, w0, 30) & 63u;
+#pragma unroll
+  for (int j = 6; j < 10; ++j) g[j] = (w1 >> (6 * j - 32)) & 63u;
+  g[10] = __builtin_amdgcn_alignbit(w2, w1, 28) & 63u;
+#pragma unroll
+  for (int j = 11; j < 16; ++j) g[j] = (w2 >> (6 * j - 64)) & 63u;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    s = lds_u16_at((s + g[j]) << 1);
+    acc |= s;
+  }
+  c = acc & 1u;
+  return s;
+}
+
+// Runs the words of block `b` (first base `base`) that hold bases in
+// [lo, hi).  CHECKED = false promises the whole block lies in [lo, hi).  BLK
+// is any register block with WORDS words and word(w, cols, rst).
+template <class BLK, int SHIFT, int STEP, bool CHECKED, class Sink>
+__device__ __forceinline__ uint32_t run_words(const Tab& tb, uint32_t s, const BLK& b, uint64_t base, uint64_t lo,
+                                              uint64_t hi, Sink& sink) {
+  constexpr int W = BLK::WORDS;
+  constexpr int U = (STEP == 3 && !CHECKED) ? W / 3 : 0;  // whole 48-base units
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    uint32_t c0, r0, c1, r1, c2, r2;
+    b.word(3 * u, c0, r0);
+    b.word(3 * u + 1, c1, r1);
+    b.word(3 * u + 2, c2, r2);
+    const uint64_t p = base + 48 * u;
+    // units without resets and units inside an N run take the same walk (the
+    // latter end in q0 and report nothing), so lanes in N runs do not diverge
+    const bool all_n = (r0 & r1 & r2) == 0xFFFFu;
+    if ((r0 | r1 | r2) == 0u || all_n) {
+      uint32_t f;
+      const uint32_t e = walk48(s, c0, c1, c2, f);
+      if (all_n) {
+        s = tb.q0s;
+      } else if (__builtin_expect(f != 0u, 0)) {  // matches in the unit: replay it base by base
+        s = slow_word<SHIFT>(tb, s, c0, 0u, 0xFFFFu, p, sink);
+        s = slow_word<SHIFT>(tb, s, c1, 0u, 0xFFFFu, p + 16, sink);
+        s = slow_word<SHIFT>(tb, s, c2, 0u, 0xFFFFu, p + 32, sink);
+      } else {
+        s = e;
+      }
+    } else {
+      s = run_word<SHIFT, STEP>(tb, s, c0, r0, p, sink);
+      s = run_word<SHIFT, STEP>(tb, s, c1, r1, p + 16, sink);
+      s = run_word<SHIFT, STEP>(tb, s, c2, r2, p + 32, sink);
+    }
+  }
+#pragma unroll
+  for (int w = 3 * U; w < W; ++w) {
     uint32_t cols, rst;
     b.word(w, cols, rst);
     const uint64_t p = base + 16 * w;
@@ -503,13 +665,19 @@ __device__ __forceinline__ uint32_t run_block(const Tab& tb, uint32_t s, const B
       if (a1 <= a0) continue;
       const uint32_t act = (0xFFFFu >> (16 - a1)) & ~((1u << a0) - 1u);
       if (act != 0xFFFFu) {
-        s = word_slow<SHIFT>(tb, s, cols, rst, act, p, sink);
+        s = slow_word<SHIFT>(tb, s, cols, rst, act, p, sink);
         continue;
       }
     }
     s = run_word<SHIFT, STEP>(tb, s, cols, rst, p, sink);
   }
   return s;
+}
+
+template <int ENC, int SHIFT, int STEP, bool CHECKED, class Sink>
+__device__ __forceinline__ uint32_t run_block(const Tab& tb, uint32_t s, const Block<ENC>& b, uint64_t base,
+                                              uint64_t lo, uint64_t hi, Sink& sink) {
+  return run_words<Block<ENC>, SHIFT, STEP, CHECKED>(tb, s, b, base, lo, hi, sink);
 }
 
 // Scans [p, hi) from state s.  With HAS_FIRST, `first` already holds the
@@ -547,6 +715,53 @@ __device__ __forceinline__ uint32_t scan_range(const ScanArgs& a, const Tab& tb,
                                                Sink& sink) {
   Block<ENC> unused;
   return scan_blocks<ENC, SHIFT, STEP, false>(a, tb, s, p, hi, sink, unused);
+}
+
+// Two ranges [p0, h0) and [p1, h1) (two chunks of one lane) from s0 and s1:
+// each range's first block alone, then the whole blocks of both in lockstep
+// with their lookups interleaved, then what is left of each range alone.
+template <int ENC, int SHIFT, int STEP, class Sink>
+__device__ __forceinline__ void scan_range2(const ScanArgs& a, const Tab& tb, uint32_t& s0, uint64_t p0, uint64_t h0,
+                                            Sink& k0, uint32_t& s1, uint64_t p1, uint64_t h1, Sink& k1) {
+  using B = Block<ENC>;
+  constexpr int W = B::WORDS;
+  uint64_t b0 = h0, b1 = h1;  // first base of the next whole block of each range
+  if (p0 < h0) {
+    b0 = p0 / B::BASES * B::BASES;
+    B blk;
+    load_block<ENC>(a, b0, blk);
+    s0 = run_block<ENC, SHIFT, STEP, true>(tb, s0, blk, b0, p0, h0, k0);
+    b0 += B::BASES;
+  }
+  if (p1 < h1) {
+    b1 = p1 / B::BASES * B::BASES;
+    B blk;
+    load_block<ENC>(a, b1, blk);
+    s1 = run_block<ENC, SHIFT, STEP, true>(tb, s1, blk, b1, p1, h1, k1);
+    b1 += B::BASES;
+  }
+  for (; b0 + B::BASES <= h0 && b1 + B::BASES <= h1; b0 += B::BASES, b1 += B::BASES) {
+    B x0, x1;
+    x0.load(a, b0);
+    x1.load(a, b1);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      uint32_t c0, r0, c1, r1;
+      x0.word(w, c0, r0);
+      x1.word(w, c1, r1);
+      run_word2<SHIFT, STEP>(tb, s0, c0, r0, b0 + 16 * w, k0, s1, c1, r1, b1 + 16 * w, k1);
+    }
+  }
+  for (; b0 < h0; b0 += B::BASES) {
+    B blk;
+    load_block<ENC>(a, b0, blk);
+    s0 = run_block<ENC, SHIFT, STEP, true>(tb, s0, blk, b0, b0, h0, k0);
+  }
+  for (; b1 < h1; b1 += B::BASES) {
+    B blk;
+    load_block<ENC>(a, b1, blk);
+    s1 = run_block<ENC, SHIFT, STEP, true>(tb, s1, blk, b1, b1, h1, k1);
+  }
 }
 
 // ------------------------------------------------------------------ chunk headers

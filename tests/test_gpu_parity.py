@@ -78,10 +78,12 @@ def test_invariance_over_options(coex, enc):
         d = coex.Dfa.kmers(pats)
         expect = oracle.count_kmers(pats, oracle.byte_seq(seq))[0].tolist()
         for chunk in [1, 7, 16, 63, 64, 100, 512, 1000, 4096, n - 1, n, n + 5, 0]:
-            for (width, lookback, step) in [(0, 0, 0), (1, 1, 1), (2, 1, 2), (8, 2, 0), (64, 1, 0), (4, 8, 2)]:
-                say("invariance", enc, pats[:2], chunk, width, lookback, step)
-                got = gpu_counts(coex, d, s, chunk=chunk, width=width, lookback=lookback, step=step)
-                assert got.tolist() == expect, (pats, chunk, width, lookback, step)
+            for (width, lookback, step, chains) in [(0, 0, 0, 0), (1, 1, 1, 1), (2, 1, 2, 1), (8, 2, 0, 0),
+                                                    (64, 1, 0, 0), (4, 8, 2, 0), (0, 0, 3, 1), (1, 2, 3, 1),
+                                                    (16, 1, 3, 1), (0, 0, 3, 2), (2, 1, 2, 2), (8, 3, 3, 2)]:
+                say("invariance", enc, pats[:2], chunk, width, lookback, step, chains)
+                got = gpu_counts(coex, d, s, chunk=chunk, width=width, lookback=lookback, step=step, chains=chains)
+                assert got.tolist() == expect, (pats, chunk, width, lookback, step, chains)
 
 
 def test_positions_multi_pattern(coex):
@@ -132,6 +134,9 @@ def test_random_regexes(coex):
             say("regex", rx, chunk)
             assert gpu_counts(coex, d, s, chunk=chunk).tolist() == [m]
             assert gpu_counts(coex, d, s2, chunk=chunk).tolist() == [m]
+            if d.info().n_states <= 1023:
+                assert gpu_counts(coex, d, s, chunk=chunk, step=3).tolist() == [m]
+                assert gpu_counts(coex, d, s2, chunk=chunk, step=3).tolist() == [m]
         pos, _ = coex.find(d, s, chunk=1000)
         assert pos.cpu().numpy().tolist() == epos.tolist()
 
@@ -145,6 +150,10 @@ def test_genome_fraction(coex):
     expect = oracle.count_kmers(kmers, oracle.twobit_seq(packed, mask, n))[0]
     assert gpu_counts(coex, d, s).tolist() == expect.tolist()
     assert gpu_counts(coex, d, s, chunk=1 << 16, lookback=1, width=64).tolist() == expect.tolist()
+    assert gpu_counts(coex, d, s, step=3).tolist() == expect.tolist()
+    assert gpu_counts(coex, d, s, step=3, chunk=5000).tolist() == expect.tolist()
+    assert gpu_counts(coex, d, s, step=3, chains=2).tolist() == expect.tolist()
+    assert gpu_counts(coex, d, s, step=2, chains=2, chunk=4099).tolist() == expect.tolist()
 
 
 def _parity_table():
@@ -260,10 +269,18 @@ def test_full_genome(coex):
     d = coex.Dfa.kmers(kmers)
     s = coex.to_device(packed, n=n, encoding=coex.ENC_2BIT, nmask=mask)
     got = gpu_counts(coex, d, s)
+    got3 = gpu_counts(coex, d, s, step=3)
+    got2 = gpu_counts(coex, d, s, step=2)
+    got32 = gpu_counts(coex, d, s, step=3, chains=2)
+    got22 = gpu_counts(coex, d, s, step=2, chains=2)
     say("genome full: gpu done", int(got.sum()))
     expect = oracle.count_kmers(kmers, oracle.twobit_seq(packed, mask, n))[0]
     say("genome full: oracle done", int(expect.sum()))
     assert got.tolist() == expect.tolist()
+    assert got3.tolist() == expect.tolist()
+    assert got2.tolist() == expect.tolist()
+    assert got32.tolist() == expect.tolist()
+    assert got22.tolist() == expect.tolist()
     del s
     torch.cuda.empty_cache()
 
