@@ -492,9 +492,8 @@ def main():
     algo_bytes = w["n"] * w["bytes_per_base"]
     achieved = algo_bytes / (k_avg_ms * 1e-3) / 1e9
     # symbols per lookup of the chunk scan (the planner's default: three for
-    # 2-bit input of an automaton of at most 1023 states, else two, else one)
-    sym = args.step or (1 if info.n_states > 1024 else (3 if w["enc"] == coex.ENC_2BIT and info.n_states <= 1023
-                                                         else 2))
+    # an automaton of at most 1023 states, else two, else one)
+    sym = args.step or (1 if info.n_states > 1024 else (3 if info.n_states <= 1023 else 2))
     # lookups per base: three symbols per lookup walk 512-base blocks as ten
     # 48-base units (16 lookups) and two words (5 three- + 1 one-symbol lookup)
     per_base = {1: 1.0, 2: 0.5, 3: 172.0 / 512.0}[sym]

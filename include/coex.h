@@ -189,9 +189,14 @@ int coex_count_noalloc(const coex_dfa* dfa, const coex_seq* seq, uint64_t* count
 /* End positions of every match ("count and extract", Section III.A):
    pos_dev int64[capacity] and pattern_dev uint32[capacity] (may be NULL)
    receive the matches in ascending end position, ties by pattern id.
-   *n_found (host) receives the number of matches.  Synchronises `stream`
-   once (to read the total).  If the total exceeds `capacity`, nothing is
-   written, *n_found holds the required size and ECAPACITY is returned. */
+   *n_found (host) receives the number of matches.  One pass over the
+   sequence: the scan appends each match as it is found (end position and
+   pattern id in one key, so at most 2^24 pattern ids and 2^40 bases; beyond
+   that, or with opts->chains = 2, a second pass writes them in order);
+   the stream is synchronised once to read the total, then the keys are
+   sorted on the stream.  If the total exceeds `capacity`, *n_found holds the
+   required size, ECAPACITY is returned and the contents of pos_dev and
+   pattern_dev are unspecified. */
 int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
               uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream);
 

@@ -41,6 +41,12 @@
 
 namespace coex {
 
+// sort.hip: ordering of appended match keys (end position << 24 | pattern id)
+constexpr uint32_t kSmallSortKeys = 4096;
+size_t sort_temp_bytes(uint64_t cap);
+int sort_match_keys(const uint64_t* keys, uint64_t* tmp, uint64_t n, void* temp, size_t temp_bytes, int64_t* pos,
+                    uint32_t* pat, hipStream_t st);
+
 // ====================================================================== kernels
 __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,6 +55,7 @@ __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
     *a.fix_count = 0;
     *a.err = 0;
     *a.total = 0;
+    if (a.app_count) *a.app_count = 0;
   }
   if (counts)
     for (uint32_t i = t; i < n_counts; i += gridDim.x * blockDim.x) counts[i] = 0;
@@ -136,7 +143,8 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
     const uint64_t c = i < n_imp ? i * TILE : a.fix_list[i - n_imp];
     const uint64_t lo = c * a.chunk;
     const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-    SinkGlobal sink{a.wtab, a.acc_out_off, a.acc_out_ids, per_state ? a.pat_counts : nullptr};
+    SinkGlobal sink{a.wtab, a.acc_out_off, a.acc_out_ids, per_state ? a.pat_counts : nullptr, a.app_count, a.app_keys,
+                    a.app_cap};
     // direct: every chunk converged (no join kernels ran), so the true first
     // state is the predecessor's last state
     const uint32_t s0 = direct ? (c == 0 ? a.q0s : a.end_s[c - 1]) : a.true_start[c];
@@ -494,7 +502,8 @@ struct Plan {
   bool all_conv;  // every chunk's candidates must agree inside the window (synchronising depth)
   bool direct;    // counts only and all_conv: no non-converged maps, no join kernels
   uint64_t chunk, n_chunks, n_tiles;
-  bool hist;
+  bool hist;   // several patterns (or inexact two-symbol counts): visit histogram
+  int mode;    // what the chunk scan reports: MODE_TOTAL, MODE_HIST or MODE_POS
   int enc;
 };
 
@@ -519,14 +528,14 @@ uint32_t tail_lds_bytes(uint32_t step, const Dfa& d, uint32_t k) {
   return wide_table_bytes(step, n) + n * 16 + 2 * acc + pss_lds_bytes(d, k) + kTailRedBytes + 16;
 }
 
-TailKey tail_key(const Plan& P) { return TailKey{P.enc, (int)P.shift, (int)P.step, (int)P.chains, P.hist}; }
+TailKey tail_key(const Plan& P) { return TailKey{P.enc, (int)P.shift, (int)P.step, (int)P.chains, P.mode}; }
 
 // Resident blocks per CU of the chunk-scan kernel the plan will launch.
 uint32_t tail_blocks_per_cu(const Plan& P, const Dfa& d) {
   static std::mutex mu;
-  static std::map<std::tuple<int, uint32_t, uint32_t, uint32_t, bool, uint32_t>, int> cache;
+  static std::map<std::tuple<int, uint32_t, uint32_t, uint32_t, int, uint32_t>, int> cache;
   const uint32_t lds = tail_lds_bytes(P.step, d, P.k);
-  const auto key = std::make_tuple(P.enc, P.shift, P.step, P.chains, P.hist, lds);
+  const auto key = std::make_tuple(P.enc, P.shift, P.step, P.chains, P.mode, lds);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return (uint32_t)it->second;
@@ -536,13 +545,13 @@ uint32_t tail_blocks_per_cu(const Plan& P, const Dfa& d) {
 }
 
 int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex_opts* o, int n_cu, Plan& P,
-              bool force_hist) {
+              bool force_hist, bool positions = false) {
   P.enc = sq.encoding == COEX_ENC_2BIT ? 1 : 0;
   P.shift = dc.shift;
   if (o && o->step > 3) return COEX_EINVAL;
-  // default: three symbols per lookup for 2-bit input when the automaton has
-  // a three-symbol table (fewest dependent LDS reads per base), else two
-  const uint32_t dstep = dc.shift != 6 ? 1u : (P.enc == 1 && dc.T3[0] ? 3u : 2u);
+  // default: three symbols per lookup when the automaton has a three-symbol
+  // table (fewest dependent LDS reads per base), else two, else one
+  const uint32_t dstep = dc.shift != 6 ? 1u : (dc.T3[0] ? 3u : 2u);
   P.step = (o && o->step) ? o->step : dstep;
   if (P.step == 2 && dc.shift != 6) return COEX_EUNSUPPORTED;
   if (P.step == 3 && !dc.T3[0]) return COEX_EUNSUPPORTED;
@@ -573,6 +582,7 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
   }
   const uint64_t n = sq.n_bases;
   P.hist = force_hist || d.n_patterns > 1 || (P.step == 2 && !dc.t2_exact);
+  P.mode = positions ? MODE_POS : (P.hist ? MODE_HIST : MODE_TOTAL);
   P.block = (uint32_t)tail_block(tail_key(P));
   if (o && o->chunk) {
     P.chunk = o->chunk;
@@ -606,14 +616,21 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
 int tail_block(const TailKey& k) { return (k.step == 3 && k.chains == 1) ? 1024 : kScanBlock; }
 
 int tail_occupancy(const TailKey& k, uint32_t lds) {
-  if (k.enc == ENC_BYTE) return k.hist ? tail_occupancy_byte_hist(k, lds) : tail_occupancy_byte_count(k, lds);
-  return k.hist ? tail_occupancy_2bit_hist(k, lds) : tail_occupancy_2bit_count(k, lds);
+  if (k.enc == ENC_BYTE)
+    return k.mode == MODE_POS ? tail_occupancy_byte_pos(k, lds)
+           : k.mode == MODE_HIST ? tail_occupancy_byte_hist(k, lds) : tail_occupancy_byte_count(k, lds);
+  return k.mode == MODE_POS ? tail_occupancy_2bit_pos(k, lds)
+         : k.mode == MODE_HIST ? tail_occupancy_2bit_hist(k, lds) : tail_occupancy_2bit_count(k, lds);
 }
 
 bool tail_launch(const TailKey& k, uint32_t blocks, uint32_t lds, hipStream_t st, const ScanArgs& a) {
   if (k.enc == ENC_BYTE)
-    return k.hist ? tail_launch_byte_hist(k, blocks, lds, st, a) : tail_launch_byte_count(k, blocks, lds, st, a);
-  return k.hist ? tail_launch_2bit_hist(k, blocks, lds, st, a) : tail_launch_2bit_count(k, blocks, lds, st, a);
+    return k.mode == MODE_POS ? tail_launch_byte_pos(k, blocks, lds, st, a)
+           : k.mode == MODE_HIST ? tail_launch_byte_hist(k, blocks, lds, st, a)
+                                 : tail_launch_byte_count(k, blocks, lds, st, a);
+  return k.mode == MODE_POS ? tail_launch_2bit_pos(k, blocks, lds, st, a)
+         : k.mode == MODE_HIST ? tail_launch_2bit_hist(k, blocks, lds, st, a)
+                               : tail_launch_2bit_count(k, blocks, lds, st, a);
 }
 
 namespace {
@@ -686,8 +703,9 @@ struct Call {
 
 // emit_counts: the call returns counts only (direct mode possible).
 // noalloc: tables must already be resident, scratch is the static array.
+// positions: the chunk scan appends every match (find in one pass).
 int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* stream, bool force_hist,
-            bool need_chunk_cnt, Call& C, bool emit_counts = false, bool noalloc = false) {
+            bool need_chunk_cnt, Call& C, bool emit_counts = false, bool noalloc = false, bool positions = false) {
   if (!h || !seq) return COEX_EINVAL;
   Dfa& d = *const_cast<Dfa*>(reinterpret_cast<const Dfa*>(h));
   if (seq->encoding != COEX_ENC_BYTE && seq->encoding != COEX_ENC_2BIT) return COEX_EINVAL;
@@ -699,10 +717,12 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   if (noalloc && o && (o->flags & COEX_FLAG_TIME)) return COEX_EUNSUPPORTED;  // timing creates events
   rc = noalloc ? resident(d, C.dev, C.dc) : upload(d, C.dev, C.dc);
   if (rc) return rc;
-  rc = make_plan(d, *C.dc, *seq, o, C.n_cu, C.P, force_hist);
+  rc = make_plan(d, *C.dc, *seq, o, C.n_cu, C.P, force_hist, positions);
   if (rc) return rc;
   Plan& P = C.P;
-  P.direct = emit_counts && P.all_conv;
+  // counts and appended positions need no true first state of every chunk
+  // when all chunks converge (the fix-up takes its predecessor's last state)
+  P.direct = (emit_counts || positions) && P.all_conv;
   // chunk counts must fit the 32-bit per-chunk tail counter
   if (P.chunk > (0xFFFFFFFFull / std::max<uint32_t>(1, 2 * d.max_out + 1))) return COEX_EINVAL;
   const uint32_t S = P.shift;
@@ -734,7 +754,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   // candidate maps of non-converged chunks: only when the join kernels run
   const uint64_t nc_maps = P.direct ? 0 : nc * P.max_cand;
   size_t o_nca = take(nc_maps * 4), o_nen = take(nc_maps * 4);
-  size_t o_ts = take((nc + 1) * 4), o_tot = take(8), o_err = take(4);
+  size_t o_ts = take((nc + 1) * 4), o_tot = take(8), o_err = take(4), o_app = take(8);
   size_t o_front = take((size_t)P.n_tiles * 3 * 8);
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
   size_t o_part = need_chunk_cnt ? take((nc + kCountTile - 1) / kCountTile * 8) : 0;
@@ -792,6 +812,9 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.true_start = reinterpret_cast<uint32_t*>(w + o_ts);
   a.total = reinterpret_cast<unsigned long long*>(w + o_tot);
   a.err = reinterpret_cast<uint32_t*>(w + o_err);
+  a.app_count = positions ? reinterpret_cast<unsigned long long*>(w + o_app) : nullptr;
+  a.app_keys = nullptr;
+  a.app_cap = 0;
   a.front = reinterpret_cast<uint64_t*>(w + o_front);
   a.chunk_cnt = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_cc) : nullptr;
   C.chunk_off = need_chunk_cnt ? reinterpret_cast<uint64_t*>(w + o_co) : nullptr;
@@ -963,36 +986,95 @@ int coex_count_noalloc(const coex_dfa* dfa, const coex_seq* seq, uint64_t* count
   }
 }
 
+}  // extern "C"
+
+namespace coex {
+namespace {
+
+// find in one pass: the chunk scan and the fix-up append every match as a
+// key (end position << 24 | pattern id) to the caller's position buffer
+// (positions are final when found: the scan runs from converging points, the
+// prefixes from true first states); one synchronisation reads the total,
+// then the keys are sorted and split into positions and pattern ids.
+int find_one_pass(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
+                  uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream) {
+  Call C;
+  int rc = prepare(dfa, seq, opts, stream, false, false, C, false, false, true);
+  if (rc) return rc;
+  C.a.app_keys = reinterpret_cast<uint64_t*>(pos_dev);
+  C.a.app_cap = pos_dev ? capacity : 0;
+  run_pipeline(C, nullptr, false);
+  uint64_t total = 0;
+  uint32_t e = 0;
+  if (C.P.n_chunks) {
+    if (hipMemcpyAsync(&total, C.a.app_count, 8, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
+    if (hipMemcpyAsync(&e, C.a.err, 4, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
+  }
+  if (hipStreamSynchronize(C.st) != hipSuccess) return COEX_EDEVICE;
+  if (e) return COEX_EINTERNAL;
+  *n_found = total;
+  if (total > capacity) return COEX_ECAPACITY;
+  if (total == 0) return COEX_OK;
+  char* tmp = nullptr;
+  size_t temp_bytes = 0;
+  if (total > kSmallSortKeys) {
+    temp_bytes = sort_temp_bytes(total);
+    Workspace* wsp = nullptr;
+    rc = workspace(C.dev, stream, align_up(total * 8, 256) + temp_bytes, tmp, wsp);
+    if (rc) return rc;
+  }
+  if (sort_match_keys(reinterpret_cast<const uint64_t*>(pos_dev), reinterpret_cast<uint64_t*>(tmp), total,
+                      tmp ? tmp + align_up(total * 8, 256) : nullptr, temp_bytes, pos_dev, pattern_dev, C.st))
+    return COEX_EDEVICE;
+  return COEX_OK;
+}
+
+// find in two passes (chunk counts, their prefix, then each chunk again from
+// its true first state writing at its offset): automata with more than 2^24
+// pattern ids, sequences of 2^40 bases or more, or two chains per lane.
+int find_two_pass(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
+                  uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream) {
+  Call C;
+  int rc = prepare(dfa, seq, opts, stream, false, true, C);
+  if (rc) return rc;
+  run_pipeline(C, nullptr, false);
+  uint64_t total = 0;
+  if (C.P.n_chunks) {
+    const uint32_t tiles = (uint32_t)((C.P.n_chunks + kCountTile - 1) / kCountTile);
+    hipLaunchKernelGGL(k_count_partials, dim3(tiles), dim3(kCountTile), 0, C.st, C.a, C.count_part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kCountTile), 0, C.st, C.count_part, tiles);
+    hipLaunchKernelGGL(k_count_offsets, dim3(tiles), dim3(kCountTile), 0, C.st, C.a, C.count_part, C.chunk_off);
+  }
+  if (hipMemcpyAsync(&total, C.a.total, 8, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
+  uint32_t e = 0;
+  if (hipMemcpyAsync(&e, C.a.err, 4, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
+  if (hipStreamSynchronize(C.st) != hipSuccess) return COEX_EDEVICE;
+  if (e) return COEX_EINTERNAL;
+  *n_found = total;
+  if (total > capacity) return COEX_ECAPACITY;
+  if (total == 0) return COEX_OK;
+  C.a.pos_out = pos_dev;
+  C.a.pat_out = pattern_dev;
+  C.a.pos_cap = capacity;
+  launch_emit<0>(C);
+  if (hipGetLastError() != hipSuccess) return COEX_EDEVICE;
+  return check_err(C);
+}
+
+}  // namespace
+}  // namespace coex
+
+extern "C" {
+
 int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
               uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream) {
   if (!n_found || (capacity && !pos_dev)) return COEX_EINVAL;
+  if (!dfa || !seq) return COEX_EINVAL;
   try {
-    coex::Call C;
-    int rc = coex::prepare(dfa, seq, opts, stream, false, true, C);
-    if (rc) return rc;
-    coex::run_pipeline(C, nullptr, false);
-    uint64_t total = 0;
-    if (C.P.n_chunks) {
-      const uint32_t tiles = (uint32_t)((C.P.n_chunks + coex::kCountTile - 1) / coex::kCountTile);
-      hipLaunchKernelGGL(coex::k_count_partials, dim3(tiles), dim3(coex::kCountTile), 0, C.st, C.a, C.count_part);
-      hipLaunchKernelGGL(coex::k_scan_partials, dim3(1), dim3(coex::kCountTile), 0, C.st, C.count_part, tiles);
-      hipLaunchKernelGGL(coex::k_count_offsets, dim3(tiles), dim3(coex::kCountTile), 0, C.st, C.a, C.count_part,
-                         C.chunk_off);
-    }
-    if (hipMemcpyAsync(&total, C.a.total, 8, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
-    uint32_t e = 0;
-    if (hipMemcpyAsync(&e, C.a.err, 4, hipMemcpyDeviceToHost, C.st) != hipSuccess) return COEX_EDEVICE;
-    if (hipStreamSynchronize(C.st) != hipSuccess) return COEX_EDEVICE;
-    if (e) return COEX_EINTERNAL;
-    *n_found = total;
-    if (total > capacity) return COEX_ECAPACITY;
-    if (total == 0) return COEX_OK;
-    C.a.pos_out = pos_dev;
-    C.a.pat_out = pattern_dev;
-    C.a.pos_cap = capacity;
-    coex::launch_emit<0>(C);
-    if (hipGetLastError() != hipSuccess) return COEX_EDEVICE;
-    return coex::check_err(C);
+    const Dfa& d = *reinterpret_cast<const Dfa*>(dfa);
+    const bool one_pass = d.n_patterns <= (1u << 24) && seq->n_bases < (1ull << 40) && (!opts || opts->chains <= 1);
+    return one_pass ? coex::find_one_pass(dfa, seq, pos_dev, pattern_dev, capacity, n_found, opts, stream)
+                    : coex::find_two_pass(dfa, seq, pos_dev, pattern_dev, capacity, n_found, opts, stream);
   } catch (const std::bad_alloc&) {
     return COEX_ENOMEM;
   } catch (...) {

@@ -115,6 +115,10 @@ struct ScanArgs {
   uint32_t* rec_init;
   uint32_t* rec_last;
   uint32_t shift;             // SHIFT (state register scale)
+  // find in one pass: every match appended as end position << 24 | pattern id
+  unsigned long long* app_count;
+  uint64_t* app_keys;
+  uint64_t app_cap;
 };
 
 // ------------------------------------------------------------------ symbols
@@ -219,12 +223,20 @@ struct SinkGlobal {     // weighted count, and per-pattern counts straight to gl
   const uint32_t* out_off;     // per accepting index: its pattern ids
   const uint32_t* out_ids;
   unsigned long long* pat;     // NULL: count only
+  unsigned long long* app_count = nullptr;  // non-NULL: append (position << 24 | id) keys
+  uint64_t* app_keys = nullptr;
+  uint64_t app_cap = 0;
   uint32_t cnt = 0;
   __device__ void word(uint32_t) {}
-  __device__ void hit(uint64_t, uint32_t a) {
+  __device__ void hit(uint64_t p, uint32_t a) {
     cnt += w[a];
     if (pat)
       for (uint32_t j = out_off[a]; j < out_off[a + 1]; ++j) atomicAdd(pat + out_ids[j], 1ull);
+    if (app_count)
+      for (uint32_t j = out_off[a]; j < out_off[a + 1]; ++j) {
+        const unsigned long long i = atomicAdd(app_count, 1ull);
+        if (i < app_cap) app_keys[i] = p << 24 | out_ids[j];
+      }
   }
 };
 
@@ -297,7 +309,7 @@ __device__ __forceinline__ uint32_t word_slow(const Tab& tb, uint32_t s, uint32_
 template <int SHIFT, class Sink>
 __device__ __forceinline__ uint32_t slow_word(const Tab& tb, uint32_t s, uint32_t cols, uint32_t rst, uint32_t act,
                                               uint64_t p, Sink& sink) {
-  if constexpr (Sink::kOutline) return sink.template slow<SHIFT>(s, cols, rst, act);
+  if constexpr (Sink::kOutline) return sink.template slow<SHIFT>(s, cols, rst, act, p);
   else return word_slow<SHIFT>(tb, s, cols, rst, act, p, sink);
 }
 

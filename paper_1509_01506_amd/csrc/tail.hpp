@@ -169,9 +169,26 @@ __device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, cons
 // instead of an inlined copy of the rare path.
 typedef __attribute__((address_space(3))) uint32_t lds_u32_rw;
 
-template <int SHIFT, bool HIST>
+// What the chunk-scan kernel reports: a one-pattern weighted total, the
+// per-final-state visit histogram (several patterns), or every match as an
+// append of (end position, pattern id) keys, in no particular order (find).
+constexpr int MODE_TOTAL = 0;
+constexpr int MODE_HIST = 1;
+constexpr int MODE_POS = 2;
+
+// Appends the matches ending at position p in accepting state `acc` (its
+// pattern ids, from the output sets in global memory) as keys p << 24 | id.
+__device__ __forceinline__ void append_matches(const ScanArgs& a, uint64_t p, uint32_t acc) {
+  for (uint32_t j = a.acc_out_off[acc]; j < a.acc_out_off[acc + 1]; ++j) {
+    const unsigned long long i = atomicAdd(a.app_count, 1ull);
+    if (i < a.app_cap) a.app_keys[i] = p << 24 | a.acc_out_ids[j];
+  }
+}
+
+template <int SHIFT, int MODE>
 __device__ __noinline__ uint64_t tail_word_slow(uint32_t t1_off, uint32_t q0s, uint32_t w_off, uint32_t hist_off,
-                                                uint32_t s, uint32_t cols, uint32_t rst, uint32_t act) {
+                                                uint32_t s, uint32_t cols, uint32_t rst, uint32_t act, uint64_t p,
+                                                const ScanArgs* ap) {
   uint32_t cnt = 0;
   for (int i = 0; i < 16; ++i) {
     if (!((act >> i) & 1u)) continue;
@@ -183,29 +200,33 @@ __device__ __noinline__ uint64_t tail_word_slow(uint32_t t1_off, uint32_t q0s, u
     const uint32_t acc = e >> 16;
     if (acc) {
       cnt += lds_at(w_off + 4u * (acc - 1u));
-      if (HIST) __atomic_fetch_add((lds_u32_rw*)(uintptr_t)(hist_off + 4u * (acc - 1u)), 1u, __ATOMIC_RELAXED);
+      if (MODE == MODE_HIST)
+        __atomic_fetch_add((lds_u32_rw*)(uintptr_t)(hist_off + 4u * (acc - 1u)), 1u, __ATOMIC_RELAXED);
+      if (MODE == MODE_POS) append_matches(*ap, p + (uint64_t)i, acc - 1u);
     }
     s = e & 0xFFFFu;
   }
   return (uint64_t)s | ((uint64_t)cnt << 32);
 }
 
-template <bool HIST>
+template <int MODE>
 struct SinkTail {
-  static constexpr bool kReplay = HIST;  // one-pattern totals take exact multi-symbol counts
+  static constexpr bool kReplay = MODE != MODE_TOTAL;  // one-pattern totals take exact multi-symbol counts
   static constexpr bool kOutline = true;
   uint32_t t1_off, q0s, w_off, hist_off;
+  const ScanArgs* ap;  // output sets and the append buffer (MODE_POS)
   uint32_t cnt = 0;
   __device__ void word(uint32_t c) {
-    if (!HIST) cnt += c;
+    if (MODE == MODE_TOTAL) cnt += c;
   }
-  __device__ void hit(uint64_t, uint32_t acc) {
+  __device__ void hit(uint64_t p, uint32_t acc) {
     cnt += lds_at(w_off + 4u * acc);
-    if (HIST) __atomic_fetch_add((lds_u32_rw*)(uintptr_t)(hist_off + 4u * acc), 1u, __ATOMIC_RELAXED);
+    if (MODE == MODE_HIST) __atomic_fetch_add((lds_u32_rw*)(uintptr_t)(hist_off + 4u * acc), 1u, __ATOMIC_RELAXED);
+    if (MODE == MODE_POS) append_matches(*ap, p, acc);
   }
   template <int SHIFT>
-  __device__ uint32_t slow(uint32_t s, uint32_t cols, uint32_t rst, uint32_t act) {
-    const uint64_t r = tail_word_slow<SHIFT, HIST>(t1_off, q0s, w_off, hist_off, s, cols, rst, act);
+  __device__ uint32_t slow(uint32_t s, uint32_t cols, uint32_t rst, uint32_t act, uint64_t p) {
+    const uint64_t r = tail_word_slow<SHIFT, MODE>(t1_off, q0s, w_off, hist_off, s, cols, rst, act, p, ap);
     cnt += (uint32_t)(r >> 32);
     return (uint32_t)r;
   }
@@ -231,9 +252,8 @@ struct TailShape {
 // in LDS; a lane then walks its CH chunks with their lookups interleaved (CH
 // dependent chains of LDS reads in flight).  The first lane of a tile,
 // non-converged chunks and their successors are left to the fix-up kernel.
-// HIST: per-final-state visit histogram in LDS (several patterns); else a
-// total with exact two-symbol counts.
-template <int ENC, int SHIFT, int STEP, bool HIST, int CH>
+// MODE: what is reported (MODE_TOTAL, MODE_HIST, MODE_POS).
+template <int ENC, int SHIFT, int STEP, int MODE, int CH>
 __global__ __launch_bounds__((TailShape<STEP, CH>::kBlock))
 __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_tail(ScanArgs a) {
   static_assert(CH == 1 || CH == 2, "one or two chains per lane");
@@ -245,7 +265,7 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
   uint32_t* hist = reinterpret_cast<uint32_t*>(lds + a.lds_hist_off);
   for (uint32_t i = threadIdx.x; i < a.n_acc; i += blockDim.x) {
     wl[i] = a.wtab[i];
-    if (HIST) hist[i] = 0;
+    if (MODE == MODE_HIST) hist[i] = 0;
   }
   const uint32_t* pss_off = a.pss_off;
   const uint16_t* pss_states = a.pss_states;
@@ -260,8 +280,8 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
   __syncthreads();
   const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
   if (threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
-  using Sink = SinkTail<HIST>;
-  const Sink sink0{a.lds_t1_off, a.q0s, a.lds_w_off, a.lds_hist_off};
+  using Sink = SinkTail<MODE>;
+  const Sink sink0{a.lds_t1_off, a.q0s, a.lds_w_off, a.lds_hist_off, &a};
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // global wave
   uint64_t c[CH], lo[CH], hi[CH];
@@ -341,7 +361,7 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
       a.tail_cnt[c[j]] = out_cnt[j];
     }
   }
-  if constexpr (HIST) {
+  if constexpr (MODE == MODE_HIST) {
     // per-pattern counts: each final state's visits, added to the patterns it ends
     __syncthreads();
     if (a.pat_counts)
@@ -349,7 +369,7 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
         if (hist[i])
           for (uint32_t j = a.acc_out_off[i]; j < a.acc_out_off[i + 1]; ++j)
             atomicAdd(a.pat_counts + a.acc_out_ids[j], (unsigned long long)hist[i]);
-  } else {
+  } else if constexpr (MODE == MODE_TOTAL) {
     // one atomic per block for the joined chunks' total
     for (int o = 32; o > 0; o >>= 1) fixed_total += __shfl_down(fixed_total, o);
     uint64_t* red = reinterpret_cast<uint64_t*>(lds + a.lds_red_off);
@@ -369,7 +389,7 @@ struct TailKey {
   int shift;   // state register scale: 6 (tables of up to 1024 states) or 4
   int step;    // symbols per lookup in the main walk: 1, 2 or 3
   int chains;  // chunks walked per lane with interleaved lookups: 1 or 2
-  bool hist;   // per-final-state visit histogram (several patterns)
+  int mode;    // MODE_TOTAL, MODE_HIST or MODE_POS
 };
 
 // Threads per block of the instantiation (TailShape<step, chains>::kBlock).
@@ -379,7 +399,7 @@ int tail_occupancy(const TailKey& k, uint32_t lds);
 // Launches k_tail on `st`; false if the key has no instantiation.
 bool tail_launch(const TailKey& k, uint32_t blocks, uint32_t lds, hipStream_t st, const ScanArgs& a);
 
-// The calls above for one (encoding, histogram) pair each, defined in one
+// The calls above for one (encoding, mode) pair each, defined in one
 // translation unit per pair (tail_<enc>_<kind>.hip).
 #define COEX_TAIL_DECL(NAME)                                                                   \
   int tail_occupancy_##NAME(const TailKey& k, uint32_t lds);                                   \
@@ -387,35 +407,46 @@ bool tail_launch(const TailKey& k, uint32_t blocks, uint32_t lds, hipStream_t st
                           const ScanArgs& a);
 COEX_TAIL_DECL(byte_count)
 COEX_TAIL_DECL(byte_hist)
+COEX_TAIL_DECL(byte_pos)
 COEX_TAIL_DECL(2bit_count)
 COEX_TAIL_DECL(2bit_hist)
+COEX_TAIL_DECL(2bit_pos)
 #undef COEX_TAIL_DECL
 
-// The dispatch shared by the four translation units: every (shift, step,
-// chains) combination that is instantiated.
-template <int ENC, bool HIST, class F>
+// The dispatch shared by the translation units: every (shift, step, chains)
+// combination that is instantiated (positions: one chain per lane).
+template <int ENC, int MODE, class F>
 bool tail_dispatch(const TailKey& k, F&& f) {
+  if (MODE == MODE_POS && k.chains != 1) return false;
   if (k.shift == 6) {
-    if (k.step == 3) return k.chains == 2 ? f(k_tail<ENC, 6, 3, HIST, 2>, 768) : f(k_tail<ENC, 6, 3, HIST, 1>, 1024);
-    if (k.step == 2) return k.chains == 2 ? f(k_tail<ENC, 6, 2, HIST, 2>, 768) : f(k_tail<ENC, 6, 2, HIST, 1>, 768);
-    return k.chains == 1 && f(k_tail<ENC, 6, 1, HIST, 1>, 768);
+    if (k.step == 3) {
+      if constexpr (MODE != MODE_POS)
+        if (k.chains == 2) return f(k_tail<ENC, 6, 3, MODE, 2>, 768);
+      return f(k_tail<ENC, 6, 3, MODE, 1>, 1024);
+    }
+    if (k.step == 2) {
+      if constexpr (MODE != MODE_POS)
+        if (k.chains == 2) return f(k_tail<ENC, 6, 2, MODE, 2>, 768);
+      return f(k_tail<ENC, 6, 2, MODE, 1>, 768);
+    }
+    return k.chains == 1 && f(k_tail<ENC, 6, 1, MODE, 1>, 768);
   }
-  return k.shift == 4 && k.step == 1 && k.chains == 1 && f(k_tail<ENC, 4, 1, HIST, 1>, 768);
+  return k.shift == 4 && k.step == 1 && k.chains == 1 && f(k_tail<ENC, 4, 1, MODE, 1>, 768);
 }
 
-template <int ENC, bool HIST>
+template <int ENC, int MODE>
 int tail_occupancy_enc(const TailKey& k, uint32_t lds) {
   int blocks = 0;
-  const bool ok = tail_dispatch<ENC, HIST>(k, [&](auto kern, int block) {
+  const bool ok = tail_dispatch<ENC, MODE>(k, [&](auto kern, int block) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, block, lds) != hipSuccess) blocks = 1;
     return true;
   });
   return ok ? std::max(1, blocks) : 0;
 }
 
-template <int ENC, bool HIST>
+template <int ENC, int MODE>
 bool tail_launch_enc(const TailKey& k, uint32_t blocks, uint32_t lds, hipStream_t st, const ScanArgs& a) {
-  return tail_dispatch<ENC, HIST>(k, [&](auto kern, int block) {
+  return tail_dispatch<ENC, MODE>(k, [&](auto kern, int block) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(block), lds, st, a);
     return true;

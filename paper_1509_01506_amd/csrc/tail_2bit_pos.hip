@@ -1,0 +1,14 @@
+// k_tail instantiations for 2-bit + N mask sequences reporting appended match positions (see
+// tail.hpp); a translation unit of its own so the chunk-scan variants compile
+// in parallel.
+#include "tail.hpp"
+
+namespace coex {
+
+int tail_occupancy_2bit_pos(const TailKey& k, uint32_t lds) { return tail_occupancy_enc<ENC_2BIT, MODE_POS>(k, lds); }
+
+bool tail_launch_2bit_pos(const TailKey& k, uint32_t blocks, uint32_t lds, hipStream_t st, const ScanArgs& a) {
+  return tail_launch_enc<ENC_2BIT, MODE_POS>(k, blocks, lds, st, a);
+}
+
+}  // namespace coex

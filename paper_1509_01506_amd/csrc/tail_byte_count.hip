@@ -1,14 +1,14 @@
-// k_tail instantiations for byte sequences with one-pattern totals (see
+// k_tail instantiations for byte sequences reporting one-pattern totals (see
 // tail.hpp); a translation unit of its own so the chunk-scan variants compile
 // in parallel.
 #include "tail.hpp"
 
 namespace coex {
 
-int tail_occupancy_byte_count(const TailKey& k, uint32_t lds) { return tail_occupancy_enc<ENC_BYTE, false>(k, lds); }
+int tail_occupancy_byte_count(const TailKey& k, uint32_t lds) { return tail_occupancy_enc<ENC_BYTE, MODE_TOTAL>(k, lds); }
 
 bool tail_launch_byte_count(const TailKey& k, uint32_t blocks, uint32_t lds, hipStream_t st, const ScanArgs& a) {
-  return tail_launch_enc<ENC_BYTE, false>(k, blocks, lds, st, a);
+  return tail_launch_enc<ENC_BYTE, MODE_TOTAL>(k, blocks, lds, st, a);
 }
 
 }  // namespace coex
