@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1509_01506_amd", "csrc", f) for f in ("coex.hip", "kernels.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1509_01506_amd", "csrc", f) for f in ("coex.hip", "kernels.hpp", "tail.hpp")]
 
 
 def log(*a):
@@ -149,6 +149,26 @@ def cpu_baseline(name: str, w, gpu_counts):
     exact = [int(x) for x in counts] == [int(x) for x in gpu_counts]
     return dict({"value": round(w["n"] / dt / 1e9, 4), "unit": "Gbases/s", "cores": 1, "kind": "oracle",
                  "sample": "the whole workload (%d bases), one thread, %.1f s" % (w["n"], dt)}, **host_cpu()), exact
+
+
+def paper_method_series(w, gpu_counts, threads_list):
+    """The paper's own method on the host (coex_count_host: equal chunks, one
+    per thread, PSS, R0 record, converging point, fix-up, join) over the same
+    input, for a series of thread counts: the shape of the paper's
+    thread-scaling experiment, on this machine's host CPU."""
+    import paper_1509_01506_amd as coex
+    data, mask = w["host"]
+    rates, exact = [], True
+    for t in threads_list:
+        t0 = time.perf_counter()
+        got = coex.count_host(w["dfa"], data, n=w["n"], encoding=w["enc"], nmask=mask, threads=t)
+        dt = time.perf_counter() - t0
+        rates.append(round(w["n"] / dt / 1e9, 3))
+        exact &= [int(x) for x in got] == [int(x) for x in gpu_counts]
+        log("paper method on %d host threads: %.2f s" % (t, dt))
+    return dict({"kind": "paper_method", "unit": "Gbases/s", "threads": threads_list, "gbases_per_s": rates,
+                 "speedup_vs_1": [round(r / rates[0], 2) for r in rates], "exact": bool(exact),
+                 "sample": "the whole workload, chunks = threads"}, **host_cpu())
 
 
 def bench_batched(args, w):
@@ -527,6 +547,10 @@ def main():
         res["cpu_baseline"] = cb
         res["exact"] = exact
         log("oracle: %s; exact=%s" % (cb["sample"], exact))
+        if args.workload == "genome":
+            usable = host_cpu()["usable_cpus"]
+            series = [t for t in (1, 2, 4, 8, 16, 32, 64) if t < usable] + [usable]
+            res["cpu_paper_method"] = paper_method_series(w, gpu_counts, series)
     print(json.dumps(res), flush=True)
 
 

@@ -106,14 +106,42 @@ void run_chunk(const Ctx& C, uint64_t t, ChunkOut& out, std::vector<uint32_t>& r
     r.init = cand[0];
     r.visits.assign(C.n_acc, 0);
     uint32_t s = cand[0];
-    for (uint64_t j = 0; j < len; ++j) {
+    uint64_t j = 0;
+    for (; j < len && j < win; ++j) {
       const uint32_t e = step(C, s, C.sq.at<ENC>(lo + j));
       s = e & 0xFFFFu;
       if (e >> 16) {
         r.visits[(e >> 16) - 1] += 1;
-        if (j < win) out.r0_events.push_back({(uint32_t)j, (e >> 16) - 1});
+        out.r0_events.push_back({(uint32_t)j, (e >> 16) - 1});
       }
-      if (j < win) r0_states[j] = s;
+      r0_states[j] = s;
+    }
+    // the rest of the chunk: only the state and the visits
+    uint64_t* visits = r.visits.data();
+    const uint32_t* tab = C.tab.data();
+    if (ENC == COEX_ENC_2BIT) {
+      // eight bases (two code bytes, one mask byte) at a time once aligned
+      for (; j < len && ((lo + j) & 7); ++j) {
+        const uint32_t e = tab[(size_t)s * 5 + (uint32_t)C.sq.at<ENC>(lo + j)];
+        s = e & 0xFFFFu;
+        if (e >> 16) visits[(e >> 16) - 1] += 1;
+      }
+      for (; j + 8 <= len; j += 8) {
+        const uint64_t q = lo + j;
+        const uint32_t m = C.sq.nmask ? C.sq.nmask[q >> 3] : 0u;
+        const uint32_t codes = (uint32_t)C.sq.data[q >> 2] | (uint32_t)C.sq.data[(q >> 2) + 1] << 8;
+        for (int i = 0; i < 8; ++i) {
+          const uint32_t sym = ((m >> i) & 1u) ? 4u : (codes >> (2 * i)) & 3u;
+          const uint32_t e = tab[(size_t)s * 5 + sym];
+          s = e & 0xFFFFu;
+          if (e >> 16) visits[(e >> 16) - 1] += 1;
+        }
+      }
+    }
+    for (; j < len; ++j) {
+      const uint32_t e = tab[(size_t)s * 5 + (uint32_t)C.sq.at<ENC>(lo + j)];
+      s = e & 0xFFFFu;
+      if (e >> 16) visits[(e >> 16) - 1] += 1;
     }
     r.last = s;
     r.meet = 0;

@@ -176,19 +176,34 @@ constexpr int MODE_TOTAL = 0;
 constexpr int MODE_HIST = 1;
 constexpr int MODE_POS = 2;
 
-// Appends the matches ending at position p in accepting state `acc` (its
-// pattern ids, from the output sets in global memory) as keys p << 24 | id.
-__device__ __forceinline__ void append_matches(const ScanArgs& a, uint64_t p, uint32_t acc) {
-  for (uint32_t j = a.acc_out_off[acc]; j < a.acc_out_off[acc + 1]; ++j) {
-    const unsigned long long i = atomicAdd(a.app_count, 1ull);
-    if (i < a.app_cap) a.app_keys[i] = p << 24 | a.acc_out_ids[j];
+// Where positions-mode matches go: the output sets (global memory) and the
+// append buffer of keys end position << 24 | pattern id.
+struct AppendTo {
+  const uint32_t* out_off;
+  const uint32_t* out_ids;
+  unsigned long long* count;
+  uint64_t* keys;
+  uint64_t cap;
+};
+
+// Appends the matches ending at position p in accepting state `acc`.
+__device__ __forceinline__ void append_matches(const uint32_t* out_off, const uint32_t* out_ids,
+                                               unsigned long long* count, uint64_t* keys, uint64_t cap, uint64_t p,
+                                               uint32_t acc) {
+  for (uint32_t j = out_off[acc]; j < out_off[acc + 1]; ++j) {
+    const unsigned long long i = atomicAdd(count, 1ull);
+    if (i < cap) keys[i] = p << 24 | out_ids[j];
   }
 }
 
+// The base-by-base path of one word (reset boundaries, replays of words with
+// matches), out of line; scalar arguments only (a pointer to the kernel's
+// argument block would make the kernel copy it to private memory).
 template <int SHIFT, int MODE>
 __device__ __noinline__ uint64_t tail_word_slow(uint32_t t1_off, uint32_t q0s, uint32_t w_off, uint32_t hist_off,
                                                 uint32_t s, uint32_t cols, uint32_t rst, uint32_t act, uint64_t p,
-                                                const ScanArgs* ap) {
+                                                const uint32_t* out_off, const uint32_t* out_ids,
+                                                unsigned long long* count, uint64_t* keys, uint64_t cap) {
   uint32_t cnt = 0;
   for (int i = 0; i < 16; ++i) {
     if (!((act >> i) & 1u)) continue;
@@ -202,7 +217,7 @@ __device__ __noinline__ uint64_t tail_word_slow(uint32_t t1_off, uint32_t q0s, u
       cnt += lds_at(w_off + 4u * (acc - 1u));
       if (MODE == MODE_HIST)
         __atomic_fetch_add((lds_u32_rw*)(uintptr_t)(hist_off + 4u * (acc - 1u)), 1u, __ATOMIC_RELAXED);
-      if (MODE == MODE_POS) append_matches(*ap, p + (uint64_t)i, acc - 1u);
+      if (MODE == MODE_POS) append_matches(out_off, out_ids, count, keys, cap, p + (uint64_t)i, acc - 1u);
     }
     s = e & 0xFFFFu;
   }
@@ -214,7 +229,7 @@ struct SinkTail {
   static constexpr bool kReplay = MODE != MODE_TOTAL;  // one-pattern totals take exact multi-symbol counts
   static constexpr bool kOutline = true;
   uint32_t t1_off, q0s, w_off, hist_off;
-  const ScanArgs* ap;  // output sets and the append buffer (MODE_POS)
+  AppendTo app;  // MODE_POS
   uint32_t cnt = 0;
   __device__ void word(uint32_t c) {
     if (MODE == MODE_TOTAL) cnt += c;
@@ -222,11 +237,17 @@ struct SinkTail {
   __device__ void hit(uint64_t p, uint32_t acc) {
     cnt += lds_at(w_off + 4u * acc);
     if (MODE == MODE_HIST) __atomic_fetch_add((lds_u32_rw*)(uintptr_t)(hist_off + 4u * acc), 1u, __ATOMIC_RELAXED);
-    if (MODE == MODE_POS) append_matches(*ap, p, acc);
+    if (MODE == MODE_POS) append_matches(app.out_off, app.out_ids, app.count, app.keys, app.cap, p, acc);
   }
   template <int SHIFT>
   __device__ uint32_t slow(uint32_t s, uint32_t cols, uint32_t rst, uint32_t act, uint64_t p) {
-    const uint64_t r = tail_word_slow<SHIFT, MODE>(t1_off, q0s, w_off, hist_off, s, cols, rst, act, p, ap);
+    uint64_t r;
+    if constexpr (MODE == MODE_POS)
+      r = tail_word_slow<SHIFT, MODE>(t1_off, q0s, w_off, hist_off, s, cols, rst, act, p, app.out_off, app.out_ids,
+                                      app.count, app.keys, app.cap);
+    else
+      r = tail_word_slow<SHIFT, MODE>(t1_off, q0s, w_off, hist_off, s, cols, rst, act, p, nullptr, nullptr, nullptr,
+                                      nullptr, 0);
     cnt += (uint32_t)(r >> 32);
     return (uint32_t)r;
   }
@@ -281,7 +302,8 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
   const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
   if (threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
   using Sink = SinkTail<MODE>;
-  const Sink sink0{a.lds_t1_off, a.q0s, a.lds_w_off, a.lds_hist_off, &a};
+  const Sink sink0{a.lds_t1_off, a.q0s, a.lds_w_off, a.lds_hist_off,
+                   AppendTo{a.acc_out_off, a.acc_out_ids, a.app_count, a.app_keys, a.app_cap}};
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // global wave
   uint64_t c[CH], lo[CH], hi[CH];
