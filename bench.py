@@ -14,7 +14,7 @@ for the dominant kernel (the speculation + chunk scan kernel, timed with HIP
 events on its stream inside the timed region), and a CPU baseline (the oracle,
 single thread, over the same sequence, which doubles as the exactness check).
 
-  python bench.py [--steps K] [--warmup W] [--workload genome|mid|small]
+  python bench.py [--steps K] [--warmup W] [--workload genome|mid|small|batched|serving|parity]
 """
 from __future__ import annotations
 
@@ -100,6 +100,17 @@ def build_workload(name: str):
             bytes_per_base=0.375, find=False,
             desc="genome: 3.2e9 Markov bases (GC 0.41, 1% N runs), 2-bit packed + 1-bit N mask; "
                  "64 random 12-mers as one Aho-Corasick automaton; per-pattern counts")
+    if name == "parity":
+        packed, mask, _ = configs.genome()
+        n = configs.GENOME_N
+        delta = np.array([1, 0, 0, 0, 0, 1, 1, 1], np.uint32)
+        table = (delta, 0, np.array([0, 0, 1], np.uint32), np.array([0], np.uint32))
+        return dict(
+            n=n, enc=coex.ENC_2BIT, host=(packed, mask), dfa=coex.Dfa.table(*table, 1), table=table, patterns=None,
+            chunk=0, bytes_per_base=0.375, find=False,
+            desc="parity: the genome workload's 3.2e9 bases through the two-state parity automaton "
+                 "(odd number of A since the last N), which has no synchronising word: no chunk converges, "
+                 "every chunk's candidates run to its end and the join composes every chunk's map")
     if name == "mid":
         seq, rx = configs.mid()
         return dict(n=seq.size, enc=coex.ENC_BYTE, host=(seq, None), dfa=coex.Dfa.regex(rx), patterns=rx, chunk=0,
@@ -141,6 +152,9 @@ def cpu_baseline(name: str, w, gpu_counts):
         packed, mask = w["host"]
         seq = oracle.twobit_seq(packed, mask, w["n"])
         counts = oracle.count_kmers(w["patterns"], seq)[0]
+    elif name == "parity":
+        packed, mask = w["host"]
+        counts = oracle.scan_table(oracle.make_table(*w["table"], 1), oracle.twobit_seq(packed, mask, w["n"]))[0]
     elif name == "mid":
         counts = np.array([oracle.Regex(w["patterns"]).scan(oracle.byte_seq(w["host"][0]))[0]], dtype=np.uint64)
     else:
@@ -421,7 +435,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small", "batched", "serving"])
+    ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small", "batched", "serving", "parity"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--clock-warmup-s", type=float, default=0.5,
                     help="untimed steps for this many seconds before the warm-up steps (sustained clocks)")

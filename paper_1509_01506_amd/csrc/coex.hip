@@ -11,8 +11,9 @@
 //   k_nonconv    chunks that did not converge inside the window: every
 //                candidate runs to the chunk end (the paper's non-converged
 //                runs), giving the chunk's state map on its candidates;
-//   k_compose    the join: true first state of every chunk from its
-//                predecessor's last state (constant maps absorb the chain);
+//   k_join_*     the join: true first state of every chunk from its
+//                predecessor's last state, as a scan over the non-converged
+//                chunks' maps (composed kJoinFan at a time per level);
 //   k_fixup      recounts [chunk start, converging point) from the true first
 //                state and checks it reaches the converged state (count
 //                fix-up of Algorithm 1 in an equivalent form).
@@ -61,46 +62,235 @@ __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
     for (uint32_t i = t; i < n_counts; i += gridDim.x * blockDim.x) counts[i] = 0;
 }
 
-// Non-converged chunks: one wave per chunk, one lane per candidate, each run
-// to the chunk end (tables in global memory; this is the rare path).
+// Weighted match count of one run: exact per-word counts from the
+// two-symbol table, weights of single matches (one-symbol steps) otherwise.
+struct SinkCount {
+  static constexpr bool kReplay = false;
+  static constexpr bool kOutline = false;
+  const uint32_t* w;
+  uint32_t cnt = 0;
+  __device__ void word(uint32_t c) { cnt += c; }
+  __device__ void hit(uint64_t, uint32_t acc) { cnt += w[acc]; }
+};
+
+// Non-converged chunks: every candidate runs to the chunk end (the paper's
+// runs that never meet R0), giving the chunk's map on its candidates and each
+// run's match count.  Lanes take (chunk, candidate) pairs, G = a power of two
+// at least the largest candidate list per chunk.  STEP 2 (two symbols per
+// lookup, exact counts in the entries) needs the two-symbol table at LDS
+// address 0, the one-symbol table after it.
 template <int ENC, int SHIFT, int STEP>
 __global__ __launch_bounds__(256) void k_nonconv(ScanArgs a) {
-  static_assert(STEP == 1, "one symbol per lookup");
+  static_assert(STEP == 1 || STEP == 2, "one or two symbols per lookup");
   extern __shared__ __align__(16) char lds[];
   if (*a.nc_count == 0u) return;  // the common case: every chunk converged
-  copy_to_lds(lds, a.T1, a.n_states * 16u);
+  const uint32_t t1_at = STEP == 2 ? a.n_states * 64u : 0u;
+  if (STEP == 2) copy_to_lds(lds, a.T2, a.n_states * 64u);
+  copy_to_lds(lds + t1_at, a.T1, a.n_states * 16u);
   __syncthreads();
-  const Tab tb{nullptr, lds, a.q0s};
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  const uint32_t n_nc = *a.nc_count;
-  for (uint32_t slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); slot < n_nc; slot += waves) {
-    const uint64_t c = a.nc_chunk[slot];
+  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
+  const Tab tb{STEP == 2 ? lds : nullptr, lds + t1_at, a.q0s};
+  const uint32_t G = a.nc_group;
+  const uint64_t n_pairs = (uint64_t)*a.nc_count * G;
+  const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
+  // every lane of a wave runs the same number of rounds (wave-uniform bound)
+  const uint64_t rounds = (n_pairs + lanes - 1) / lanes;
+  for (uint64_t r = 0; r < rounds; ++r) {
+    const uint64_t pair = r * lanes + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = pair < n_pairs;
+    const uint32_t slot = in ? (uint32_t)(pair / G) : 0u;
+    const uint32_t i = (uint32_t)(pair % G);
+    const uint64_t c = in ? a.nc_chunk[slot] : 0;
     const uint64_t lo = c * a.chunk;
-    const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-    uint32_t m, cbase, exact;
-    bool is_exact;
-    chunk_header<ENC, SHIFT>(a, tb, a.pss_off, lo, m, cbase, exact, is_exact);
-    if (lane == 0) a.nc_m[slot] = m;
-    for (uint32_t b = 0; b < m; b += 64) {
-      const uint32_t i = b + lane;
-      const bool live = i < m;
-      uint32_t s = is_exact ? exact : ((uint32_t)a.pss_states[cbase + (live ? i : 0)] << SHIFT);
-      const uint32_t s0 = s;
-      SinkGlobal none{a.wtab, nullptr, nullptr, nullptr};
-      s = scan_range<ENC, SHIFT, STEP>(a, tb, s, lo, hi, none);
-      if (live) {
-        a.nc_cand[(uint64_t)slot * a.max_cand + i] = s0;
-        a.nc_end[(uint64_t)slot * a.max_cand + i] = s;
-      }
+    const uint64_t hi = in ? (lo + a.chunk < a.n ? lo + a.chunk : a.n) : 0;
+    uint32_t m = 0, cbase = 0, exact = 0;
+    bool is_exact = false;
+    if (in) chunk_header<ENC, SHIFT>(a, tb, a.pss_off, lo, m, cbase, exact, is_exact);
+    const bool live = in && i < m;
+    if (in && i == 0) a.nc_m[slot] = m;
+    uint32_t s = is_exact ? exact : ((uint32_t)a.pss_states[cbase + (live ? i : 0)] << SHIFT);
+    const uint32_t s0 = s;
+    SinkCount cnt{a.wtab};
+    if (live) s = scan_range<ENC, SHIFT, STEP>(a, tb, s, lo, hi, cnt);
+    if (live) {
+      a.nc_cand[(uint64_t)slot * a.max_cand + i] = s0;
+      a.nc_end[(uint64_t)slot * a.max_cand + i] = s;
+      a.nc_cnt[(uint64_t)slot * a.max_cand + i] = cnt.cnt;
     }
   }
 }
 
-// The join: each chunk's first state is its predecessor's last state.  A
-// converged chunk is a constant map; runs of non-converged chunks are walked
-// in order from the nearest converged predecessor.
-__global__ void k_compose(ScanArgs a) {
+constexpr uint32_t kCountTile = 1024;
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t t = __shfl_up(v, (unsigned)o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Inclusive scan over a block of kCountTile threads; `sh` holds 16 words.
+__device__ __forceinline__ uint64_t block_incl_scan(uint64_t v, uint64_t* sh) {
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  v = wave_incl_scan(v);
+  if (lane == 63) sh[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    uint64_t x = lane < (kCountTile >> 6) ? sh[lane] : 0;
+    x = wave_incl_scan(x);
+    if (lane < (kCountTile >> 6)) sh[lane] = x;
+  }
+  __syncthreads();
+  return v + (w ? sh[w - 1] : 0);
+}
+
+// The join for chunks that did not converge (Section III.A: each chunk's
+// first state is its predecessor's last state), as a scan over function
+// composition.  Items are the non-converged chunks in sequence order (rank
+// k); item k's map M0[k][x] takes the index x of its true first state in its
+// candidate list to the index of the next item's true first state: the
+// position of its end state in the next chunk's list when that chunk is the
+// next item, else (a converged chunk in between absorbs the chain) the
+// constant index of the next item's known first state, its converged
+// predecessor's last state (0xFF in the map).  A map is a row of R bytes (R a
+// power of two, at least the largest candidate list, at most 64).  Rows are
+// composed kJoinFan at a time per level (one lane per row entry) until one
+// level has at most kJoinFan items; that level is walked in order from item
+// 0's known first index, and the indices are pushed back down.
+constexpr uint32_t kJoinFan = 64;
+constexpr uint32_t kJoinMaxLevels = 6;  // kJoinFan^6 items > 2^32 chunks
+
+__device__ __forceinline__ uint32_t find_cand(const ScanArgs& a, uint32_t slot, uint32_t state) {
+  const uint32_t* cand = a.nc_cand + (uint64_t)slot * a.max_cand;
+  const uint32_t m = a.nc_m[slot];
+  for (uint32_t i = 0; i < m; ++i)
+    if (cand[i] == state) return i;
+  atomicOr(a.err, 1u);  // the true first state is always a candidate
+  return 0;
+}
+
+// Rank of each non-converged chunk among them: the exclusive scan of the
+// flags in three launches (sums per tile of kCountTile chunks, k_scan_partials
+// over the sums, then each tile from its offset), the order list inverted.
+__global__ __launch_bounds__(kCountTile) void k_rank_partials(ScanArgs a, uint64_t* part) {
+  __shared__ uint64_t sh[kCountTile / 64];
+  if (*a.nc_count == 0u) return;
+  const uint64_t c = (uint64_t)blockIdx.x * kCountTile + threadIdx.x;
+  const uint64_t v = c < a.n_chunks && a.conv_t[c] == NONCONV ? 1u : 0u;
+  const uint64_t incl = block_incl_scan(v, sh);
+  if (threadIdx.x == kCountTile - 1) part[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(kCountTile) void k_rank_offsets(ScanArgs a, const uint64_t* part, uint32_t* order) {
+  __shared__ uint64_t sh[kCountTile / 64];
+  if (*a.nc_count == 0u) return;
+  const uint64_t c = (uint64_t)blockIdx.x * kCountTile + threadIdx.x;
+  const bool nc = c < a.n_chunks && a.conv_t[c] == NONCONV;
+  const uint64_t incl = block_incl_scan(nc ? 1u : 0u, sh);
+  if (nc) order[part[blockIdx.x] + incl - 1] = (uint32_t)c;
+}
+
+// Level-0 maps and the known first index of every item whose predecessor
+// converged (and of item 0).
+__global__ void k_join_map0(ScanArgs a, const uint32_t* order, uint8_t* M0, uint8_t* known, uint32_t R) {
+  const uint32_t N = *a.nc_count;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = order[k];
+    const uint32_t slot = a.nc_slot[c];
+    const uint32_t m = a.nc_m[slot];
+    if (c == 0 || a.conv_t[c - 1] != NONCONV)
+      known[k] = (uint8_t)find_cand(a, slot, c == 0 ? a.q0s : a.end_s[c - 1]);
+    uint8_t* row = M0 + k * R;
+    if (c + 1 < a.n_chunks && a.conv_t[c + 1] == NONCONV) {
+      const uint32_t nslot = a.nc_slot[c + 1];
+      for (uint32_t i = 0; i < m; ++i) row[i] = (uint8_t)find_cand(a, nslot, a.nc_end[(uint64_t)slot * a.max_cand + i]);
+    } else {
+      for (uint32_t i = 0; i < m; ++i) row[i] = 0xFFu;
+    }
+  }
+}
+
+// One step through map row y of item j (of a level whose items each cover
+// `level_div` level-0 items, n_lvl of them): 0xFF (level 0 only) is the next
+// item's known index.  Indices no candidate has stay inside the row.
+__device__ __forceinline__ uint32_t join_step(uint32_t y, uint64_t j, uint64_t n_lvl, uint64_t level_div,
+                                              const uint8_t* known, uint32_t R) {
+  const uint32_t x = y == 0xFFu ? (j + 1 < n_lvl ? known[(j + 1) * level_div] : 0u) : y;
+  return x < R ? x : 0u;
+}
+
+__device__ __forceinline__ uint64_t join_items(uint32_t n, uint64_t level_div) { return (n + level_div - 1) / level_div; }
+
+// Composition of kJoinFan consecutive rows of the level below into one row
+// of the level above: lane (K, x) follows index x through them.
+__global__ void k_join_up(const uint32_t* n_dev, uint64_t level_div, const uint8_t* below, uint8_t* up,
+                          const uint8_t* known, uint32_t R) {
+  const uint64_t n_below = join_items(*n_dev, level_div);
+  const uint64_t n_up = (n_below + kJoinFan - 1) / kJoinFan;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_up * R;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t K = t / R;
+    uint32_t x = (uint32_t)(t % R);
+    const uint64_t end = (K + 1) * kJoinFan < n_below ? (K + 1) * kJoinFan : n_below;
+    for (uint64_t j = K * kJoinFan; j < end; ++j) x = join_step(below[j * R + x], j, n_below, level_div, known, R);
+    up[t] = (uint8_t)x;
+  }
+}
+
+// The top level walked in order by one thread from item 0's known index.
+__global__ void k_join_top(const uint32_t* n_dev, uint64_t level_div, const uint8_t* top, const uint8_t* known,
+                           uint8_t* x_top, uint32_t R) {
+  const uint64_t n = join_items(*n_dev, level_div);
+  if (n == 0) return;
+  uint32_t x = known[0] < R ? known[0] : 0u;
+  for (uint64_t K = 0; K < n; ++K) {
+    x_top[K] = (uint8_t)x;
+    x = join_step(top[K * R + x], K, n, level_div, known, R);
+  }
+}
+
+// First index of every item of the level below from its parent's.
+__global__ void k_join_down(const uint32_t* n_dev, uint64_t level_div, const uint8_t* below, const uint8_t* x_up,
+                            uint8_t* x_below, const uint8_t* known, uint32_t R) {
+  const uint64_t n_below = join_items(*n_dev, level_div);
+  const uint64_t n_up = (n_below + kJoinFan - 1) / kJoinFan;
+  for (uint64_t K = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; K < n_up; K += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t x = x_up[K];
+    const uint64_t end = (K + 1) * kJoinFan < n_below ? (K + 1) * kJoinFan : n_below;
+    for (uint64_t j = K * kJoinFan; j < end; ++j) {
+      x_below[j] = (uint8_t)x;
+      x = join_step(below[j * R + x], j, n_below, level_div, known, R);
+    }
+  }
+}
+
+// True first states: each non-converged chunk and the chunk after it from the
+// item's index; a chunk after a converged chunk from that chunk's last state.
+__global__ void k_join_finish(ScanArgs a, const uint32_t* order, const uint8_t* x0) {
+  const uint32_t N = *a.nc_count;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = order[k];
+    const uint32_t slot = a.nc_slot[c];
+    const uint32_t x = x0[k] < a.nc_m[slot] ? x0[k] : 0u;
+    a.true_start[c] = a.nc_cand[(uint64_t)slot * a.max_cand + x];
+    a.true_start[c + 1] = a.nc_end[(uint64_t)slot * a.max_cand + x];
+  }
+  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= a.n_chunks;
+       c += (uint64_t)gridDim.x * blockDim.x)
+    if (c == 0) {
+      if (a.n_chunks == 0 || a.conv_t[0] != NONCONV) a.true_start[0] = a.q0s;
+    } else if (a.conv_t[c - 1] != NONCONV) {
+      a.true_start[c] = a.end_s[c - 1];
+    }
+}
+
+// The join walked in order from each converged chunk (one thread per run of
+// non-converged chunks): automata whose candidate lists are wider than the
+// composed maps' rows (more than kJoinFan possible starting states).
+__global__ void k_compose_serial(ScanArgs a) {
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c > a.n_chunks) return;
   if (c > 0 && a.conv_t[c - 1] == NONCONV) return;
@@ -108,16 +298,7 @@ __global__ void k_compose(ScanArgs a) {
   a.true_start[c] = s;
   for (uint64_t cc = c; cc < a.n_chunks && a.conv_t[cc] == NONCONV; ++cc) {
     const uint32_t slot = a.nc_slot[cc];
-    const uint32_t m = a.nc_m[slot];
-    const uint32_t* cand = a.nc_cand + (uint64_t)slot * a.max_cand;
-    uint32_t i = 0;
-    while (i < m && cand[i] != s) ++i;
-    if (i == m) {
-      atomicOr(a.err, 1u);
-      s = a.q0s;
-    } else {
-      s = a.nc_end[(uint64_t)slot * a.max_cand + i];
-    }
+    s = a.nc_end[(uint64_t)slot * a.max_cand + find_cand(a, slot, s)];
     a.true_start[cc + 1] = s;
   }
 }
@@ -153,6 +334,12 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
     if (direct && ct == NONCONV) {
       atomicOr(a.err, 128u);
       mine = 0;
+    } else if (ct == NONCONV && !per_state && !a.app_count) {
+      // a weighted total only: the candidate runs counted the chunk
+      const uint32_t slot = a.nc_slot[c];
+      const uint64_t at = (uint64_t)slot * a.max_cand + find_cand(a, slot, s0);
+      if (a.nc_end[at] != a.true_start[c + 1]) atomicOr(a.err, 2u);
+      mine = a.nc_cnt[at];
     } else if (ct == NONCONV) {
       const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
       if (e != a.true_start[c + 1]) atomicOr(a.err, 2u);
@@ -180,33 +367,6 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
 // (k_scan_partials, one block), then a scan of every tile's own chunks from
 // its tile offset (k_count_offsets).  The last tile writes the total to
 // *a.total.
-constexpr uint32_t kCountTile = 1024;
-
-__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint64_t t = __shfl_up(v, (unsigned)o);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-// Inclusive scan over a block of kCountTile threads; `sh` holds 16 words.
-__device__ __forceinline__ uint64_t block_incl_scan(uint64_t v, uint64_t* sh) {
-  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  v = wave_incl_scan(v);
-  if (lane == 63) sh[w] = v;
-  __syncthreads();
-  if (w == 0) {
-    uint64_t x = lane < (kCountTile >> 6) ? sh[lane] : 0;
-    x = wave_incl_scan(x);
-    if (lane < (kCountTile >> 6)) sh[lane] = x;
-  }
-  __syncthreads();
-  return v + (w ? sh[w - 1] : 0);
-}
-
 __global__ __launch_bounds__(kCountTile) void k_count_partials(ScanArgs a, uint64_t* part) {
   __shared__ uint64_t sh[kCountTile / 64];
   const uint64_t i = (uint64_t)blockIdx.x * kCountTile + threadIdx.x;
@@ -288,6 +448,7 @@ struct DeviceCopy {
   size_t bytes = 0;
   uint32_t shift = 6;
   bool t2_exact = true;
+  bool dense = false;  // accepting states are visited in many three-symbol steps (see match_density)
   // per encoding [0] = byte, [1] = 2-bit
   const uint32_t* T2[2] = {nullptr, nullptr};
   const uint16_t* T3[2] = {nullptr, nullptr};  // automata of at most kMaxStatesStep3 states
@@ -344,6 +505,26 @@ const int kOrdByte[4] = {0, 1, 3, 2};  // A C T G ((byte >> 1) & 3)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Fraction of three-symbol steps that visit an accepting state, on a fixed
+// pseudo-random sequence of 3 * 8192 symbols run from q0.  Three symbols per
+// lookup pay a base-by-base replay for every 48-base unit holding a match, so
+// automata that match often (more than one step in 16) walk two symbols per
+// lookup, whose entries carry exact counts.
+double match_density(const Dfa& d) {
+  uint32_t s = d.q0, x = 12345u, hits = 0;
+  constexpr uint32_t kSteps = 8192;
+  for (uint32_t i = 0; i < kSteps; ++i) {
+    bool hit = false;
+    for (int j = 0; j < 3; ++j) {
+      x = x * 1664525u + 1013904223u;  // LCG (Numerical Recipes constants)
+      s = d.delta[s * 4 + (x >> 30)];
+      hit |= d.acc_index[s] >= 0;
+    }
+    hits += hit ? 1u : 0u;
+  }
+  return (double)hits / kSteps;
+}
+
 int upload(Dfa& d, int dev, DeviceCopy*& out) {
   std::lock_guard<std::mutex> lk(d.mu);
   if ((int)d.dev.size() > dev && d.dev[dev]) { out = d.dev[dev]; return COEX_OK; }
@@ -352,6 +533,7 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
   dc->device = dev;
   dc->shift = n <= kMaxStatesStep2 ? 6 : 4;
   dc->t2_exact = d.max_out <= 15;
+  dc->dense = match_density(d) > 1.0 / 16;
   const uint32_t S = dc->shift;
   std::vector<uint32_t> w(d.n_accepting);
   for (uint32_t i = 0; i < d.n_accepting; ++i) {
@@ -499,6 +681,9 @@ int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) 
 
 struct Plan {
   uint32_t shift, step, chains, block, k, group, max_cand, blocks, lds_bytes;
+  uint32_t join_r;       // map row bytes of the parallel join (0: the serial join, more than kJoinFan candidates)
+  uint32_t join_levels;  // composed levels above the level-0 maps
+  bool t2_exact;         // two-symbol entries carry exact weighted counts
   bool all_conv;  // every chunk's candidates must agree inside the window (synchronising depth)
   bool direct;    // counts only and all_conv: no non-converged maps, no join kernels
   uint64_t chunk, n_chunks, n_tiles;
@@ -548,10 +733,12 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
               bool force_hist, bool positions = false) {
   P.enc = sq.encoding == COEX_ENC_2BIT ? 1 : 0;
   P.shift = dc.shift;
+  P.t2_exact = dc.shift == 6 && dc.t2_exact;
   if (o && o->step > 3) return COEX_EINVAL;
   // default: three symbols per lookup when the automaton has a three-symbol
-  // table (fewest dependent LDS reads per base), else two, else one
-  const uint32_t dstep = dc.shift != 6 ? 1u : (dc.T3[0] ? 3u : 2u);
+  // table (fewest dependent LDS reads per base) and matches rarely, else two,
+  // else one
+  const uint32_t dstep = dc.shift != 6 ? 1u : (dc.T3[0] && !dc.dense ? 3u : 2u);
   P.step = (o && o->step) ? o->step : dstep;
   if (P.step == 2 && dc.shift != 6) return COEX_EUNSUPPORTED;
   if (P.step == 3 && !dc.T3[0]) return COEX_EUNSUPPORTED;
@@ -593,8 +780,8 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
     const uint64_t lanes = (uint64_t)n_cu * tail_blocks_per_cu(P, d) * P.block * P.chains;
     uint64_t c = (n + lanes - 1) / std::max<uint64_t>(1, lanes);
     c = std::max<uint64_t>(512, align_up(c, 512));
-    // bound the non-converged scratch (chunks * candidates * 8 bytes) to 512 MiB
-    while ((n / c + 1) * (uint64_t)mx * 8 > (512ull << 20)) c *= 2;
+    // bound the non-converged scratch (chunks * candidates * 12 bytes) to 768 MiB
+    while ((n / c + 1) * (uint64_t)mx * 12 > (768ull << 20)) c *= 2;
     P.chunk = c;
   }
   P.n_chunks = n == 0 ? 0 : (n + P.chunk - 1) / P.chunk;
@@ -657,9 +844,53 @@ void launch_scan(const Plan& P, const ScanArgs& a, hipStream_t st, Workspace* ti
   if (ev) (void)hipEventRecord(ev->second, st);
 }
 
+// Buffers of the parallel join (level l: items of kJoinFan^l level-0 items).
+struct JoinBufs {
+  uint32_t* order = nullptr;  // rank -> chunk
+  uint8_t* known = nullptr;   // known first index of items after a converged chunk
+  uint64_t* part = nullptr;   // rank partial sums per tile of kCountTile chunks
+  uint8_t* map[kJoinMaxLevels + 1] = {};
+  uint8_t* x[kJoinMaxLevels + 1] = {};
+};
+
+uint32_t grid_for(uint64_t threads, int n_cu) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((threads + 255) / 256, (uint64_t)n_cu * 16));
+}
+
+void launch_join(const Plan& P, ScanArgs& a, const JoinBufs& J, int n_cu, hipStream_t st) {
+  const uint64_t nc = P.n_chunks;
+  if (!P.join_r) {
+    hipLaunchKernelGGL(k_compose_serial, dim3(grid_for(nc + 1, n_cu)), dim3(256), 0, st, a);
+    return;
+  }
+  const uint32_t R = P.join_r;
+  const uint32_t tiles = (uint32_t)((nc + kCountTile - 1) / kCountTile);
+  hipLaunchKernelGGL(k_rank_partials, dim3(tiles), dim3(kCountTile), 0, st, a, J.part);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kCountTile), 0, st, J.part, tiles);
+  hipLaunchKernelGGL(k_rank_offsets, dim3(tiles), dim3(kCountTile), 0, st, a, (const uint64_t*)J.part, J.order);
+  hipLaunchKernelGGL(k_join_map0, dim3(grid_for(nc, n_cu)), dim3(256), 0, st, a, (const uint32_t*)J.order, J.map[0],
+                     J.known, R);
+  uint64_t div = 1;
+  for (uint32_t l = 1; l <= P.join_levels; ++l, div *= kJoinFan) {
+    const uint64_t n_up = (nc + div * kJoinFan - 1) / (div * kJoinFan);
+    hipLaunchKernelGGL(k_join_up, dim3(grid_for(n_up * R, n_cu)), dim3(256), 0, st, (const uint32_t*)a.nc_count, div,
+                       (const uint8_t*)J.map[l - 1], J.map[l], (const uint8_t*)J.known, R);
+  }
+  hipLaunchKernelGGL(k_join_top, dim3(1), dim3(1), 0, st, (const uint32_t*)a.nc_count, div,
+                     (const uint8_t*)J.map[P.join_levels], (const uint8_t*)J.known, J.x[P.join_levels], R);
+  for (uint32_t l = P.join_levels; l >= 1; --l) {
+    div /= kJoinFan;
+    const uint64_t n_up = (nc + div * kJoinFan - 1) / (div * kJoinFan);
+    hipLaunchKernelGGL(k_join_down, dim3(grid_for(n_up, n_cu)), dim3(256), 0, st, (const uint32_t*)a.nc_count, div,
+                       (const uint8_t*)J.map[l - 1], (const uint8_t*)J.x[l], J.x[l - 1], (const uint8_t*)J.known, R);
+  }
+  hipLaunchKernelGGL(k_join_finish, dim3(grid_for(nc + 1, n_cu)), dim3(256), 0, st, a, (const uint32_t*)J.order,
+                     (const uint8_t*)J.x[0]);
+}
+
 template <int ENC, int SHIFT>
-void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint64_t* counts, bool emit_counts,
-                     Workspace* timed) {
+void launch_pipeline(const Plan& P, ScanArgs& a, const JoinBufs& J, int n_cu, hipStream_t st, uint64_t* counts,
+                     bool emit_counts, Workspace* timed) {
   // counts go straight to the caller's buffer (zeroed here): per pattern from
   // the visit histograms, or the total of a one-pattern automaton
   a.pat_counts = emit_counts && P.hist ? reinterpret_cast<unsigned long long*>(counts) : nullptr;
@@ -667,20 +898,32 @@ void launch_pipeline(const Plan& P, ScanArgs& a, int n_cu, hipStream_t st, uint6
   hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, a, counts, emit_counts ? a.n_patterns : 0u);
   if (P.n_chunks == 0) return;
   launch_scan(P, a, st, timed);
-  constexpr int DSTEP = 1;  // non-converged runs and prefix recounts: one-symbol table staged in LDS
+  constexpr int DSTEP = 1;  // prefix recounts: one-symbol table staged in LDS
   // counts of an automaton that synchronises inside every chunk's window need
   // neither non-converged maps nor the true first state of every chunk (the
   // fix-up reads its predecessor's last state); positions and records do
   const bool direct = P.direct;
   if (!direct) {
-    const uint32_t nc_lds = a.n_states * 16u + 16u;
-    (void)hipFuncSetAttribute((const void*)k_nonconv<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)nc_lds);
-    hipLaunchKernelGGL((k_nonconv<ENC, SHIFT, DSTEP>), dim3(std::max(1, n_cu)), dim3(256), nc_lds, st, a);
-    const uint32_t cb = (uint32_t)((P.n_chunks + 1 + 255) / 256);
-    hipLaunchKernelGGL(k_compose, dim3(cb), dim3(256), 0, st, a);
+    // one lane per (chunk, candidate) pair, up to 8 blocks per CU; two symbols
+    // per lookup when the two-symbol table counts exactly
+    const uint64_t pairs = P.n_chunks * a.nc_group;
+    const uint32_t nb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((pairs + 255) / 256, (uint64_t)n_cu * 8));
+    auto go = [&](auto kern, uint32_t lds) {
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(256), lds, st, a);
+    };
+    if constexpr (SHIFT == 6) {
+      if (P.t2_exact) go(k_nonconv<ENC, 6, 2>, a.n_states * 80u + 16u);
+      else go(k_nonconv<ENC, 6, 1>, a.n_states * 16u + 16u);
+    } else {
+      go(k_nonconv<ENC, SHIFT, 1>, a.n_states * 16u + 16u);
+    }
+    launch_join(P, a, J, n_cu, st);
   }
-  const uint32_t fb = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P.n_chunks + 255) / 256, n_cu));
+  // every chunk of a tile's first lane and every chunk on the fix list: up to
+  // 8 blocks per CU (blocks past the device's item count return at once)
+  const uint32_t fb = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>((P.n_tiles + (direct ? 0 : P.n_chunks) + 255) / 256, (uint64_t)n_cu * 8));
   const uint32_t t1_lds = a.n_states * 16u + 16u;
   (void)hipFuncSetAttribute((const void*)k_fixup<ENC, SHIFT, DSTEP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)t1_lds);
@@ -699,6 +942,7 @@ struct Call {
   char* ws = nullptr;
   uint64_t* chunk_off = nullptr;
   uint64_t* count_part = nullptr;  // per tile of kCountTile chunks: its count
+  JoinBufs join;
 };
 
 // emit_counts: the call returns counts only (direct mode possible).
@@ -753,7 +997,30 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   size_t o_fxc = take(4), o_fxl = take(nc * 4);
   // candidate maps of non-converged chunks: only when the join kernels run
   const uint64_t nc_maps = P.direct ? 0 : nc * P.max_cand;
-  size_t o_nca = take(nc_maps * 4), o_nen = take(nc_maps * 4);
+  size_t o_nca = take(nc_maps * 4), o_nen = take(nc_maps * 4), o_ncn = take(nc_maps * 4);
+  // the parallel join: order, known indices, rank partials, maps and indices per level
+  P.join_r = 0;
+  P.join_levels = 0;
+  size_t o_jord = 0, o_jkn = 0, o_jpart = 0, o_jmap[kJoinMaxLevels + 1] = {}, o_jx[kJoinMaxLevels + 1] = {};
+  if (!P.direct && P.max_cand <= kJoinFan) {
+    uint32_t r = 1;
+    while (r < P.max_cand) r <<= 1;
+    P.join_r = r;
+    uint64_t items = nc;
+    while (items > kJoinFan) {
+      items = (items + kJoinFan - 1) / kJoinFan;
+      ++P.join_levels;
+    }
+    o_jord = take(nc * 4);
+    o_jkn = take(nc);
+    o_jpart = take((nc + kCountTile - 1) / kCountTile * 8);
+    uint64_t n_l = nc;
+    for (uint32_t l = 0; l <= P.join_levels; ++l) {
+      o_jmap[l] = take(n_l * r);
+      o_jx[l] = take(n_l);
+      n_l = (n_l + kJoinFan - 1) / kJoinFan;
+    }
+  }
   size_t o_ts = take((nc + 1) * 4), o_tot = take(8), o_err = take(4), o_app = take(8);
   size_t o_front = take((size_t)P.n_tiles * 3 * 8);
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
@@ -809,6 +1076,22 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.nc_m = reinterpret_cast<uint32_t*>(w + o_nm);
   a.nc_cand = reinterpret_cast<uint32_t*>(w + o_nca);
   a.nc_end = reinterpret_cast<uint32_t*>(w + o_nen);
+  a.nc_cnt = reinterpret_cast<uint32_t*>(w + o_ncn);
+  {
+    uint32_t g = 1;
+    while (g < P.max_cand) g <<= 1;
+    a.nc_group = g;
+  }
+  C.join = JoinBufs{};
+  if (P.join_r) {
+    C.join.order = reinterpret_cast<uint32_t*>(w + o_jord);
+    C.join.known = reinterpret_cast<uint8_t*>(w + o_jkn);
+    C.join.part = reinterpret_cast<uint64_t*>(w + o_jpart);
+    for (uint32_t l = 0; l <= P.join_levels; ++l) {
+      C.join.map[l] = reinterpret_cast<uint8_t*>(w + o_jmap[l]);
+      C.join.x[l] = reinterpret_cast<uint8_t*>(w + o_jx[l]);
+    }
+  }
   a.true_start = reinterpret_cast<uint32_t*>(w + o_ts);
   a.total = reinterpret_cast<unsigned long long*>(w + o_tot);
   a.err = reinterpret_cast<uint32_t*>(w + o_err);
@@ -832,11 +1115,11 @@ void run_pipeline(Call& C, uint64_t* counts, bool emit_counts) {
   const Plan& P = C.P;
   Workspace* t = C.timed ? C.wsp : nullptr;
   if (P.shift == 6) {
-    if (b) launch_pipeline<ENC_BYTE, 6>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
-    else launch_pipeline<ENC_2BIT, 6>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
+    if (b) launch_pipeline<ENC_BYTE, 6>(P, C.a, C.join, C.n_cu, C.st, counts, emit_counts, t);
+    else launch_pipeline<ENC_2BIT, 6>(P, C.a, C.join, C.n_cu, C.st, counts, emit_counts, t);
   } else {
-    if (b) launch_pipeline<ENC_BYTE, 4>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
-    else launch_pipeline<ENC_2BIT, 4>(P, C.a, C.n_cu, C.st, counts, emit_counts, t);
+    if (b) launch_pipeline<ENC_BYTE, 4>(P, C.a, C.join, C.n_cu, C.st, counts, emit_counts, t);
+    else launch_pipeline<ENC_2BIT, 4>(P, C.a, C.join, C.n_cu, C.st, counts, emit_counts, t);
   }
 }
 

@@ -78,6 +78,7 @@ struct ScanArgs {
   uint32_t k;
   uint32_t group;             // lanes per chunk in the speculation (power of two)
   uint32_t max_cand;          // largest candidate list of any chunk
+  uint32_t nc_group;          // lanes per non-converged chunk (power of two >= max_cand)
   // per-chunk outputs
   uint32_t* conv_t;           // symbols consumed to the converging point, NONCONV if none
   uint32_t* conv_s;           // state there
@@ -97,6 +98,7 @@ struct ScanArgs {
   uint32_t* nc_m;             // slot -> number of candidates
   uint32_t* nc_cand;          // slot * max_cand + i -> candidate state
   uint32_t* nc_end;           // slot * max_cand + i -> end state from that candidate
+  uint32_t* nc_cnt;           // per slot and candidate: its run's weighted match count
   uint32_t* true_start;       // n_chunks + 1
   unsigned long long* pat_counts;  // per pattern (the caller's counts), or NULL
   unsigned long long* total;  // weighted total

@@ -88,6 +88,20 @@ __device__ __forceinline__ uint32_t run_staged(const Tab& tb, uint32_t s, uint64
   return s;
 }
 
+// Slots in a list for the lanes of a wave that set `take` (all lanes of the
+// wave call it): one atomic add of the wave's count on the list's counter,
+// each lane's slot = the old value + the lanes before it that take one.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool take) {
+  const unsigned long long bm = __ballot(take);
+  if (bm == 0) return 0;
+  const int leader = __ffsll((long long)bm) - 1;
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t base = 0;
+  if ((int)lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(bm));
+  base = __shfl(base, leader);
+  return base + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
+}
+
 // Speculation for one tile of 64 chunks (one wave): possible starting states
 // from the lookback table, then rounds in which G lanes run the candidates
 // of one chunk in lockstep over its first symbols until they agree (the
@@ -151,9 +165,11 @@ __device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, cons
   }
   out_t = my_t;
   out_s = my_s;
+  // queue the non-converged chunks: one counter update per wave
+  const bool queue = valid && my_t == NONCONV;
+  const uint32_t slot = wave_append(a.nc_count, queue);
   if (!valid) return;
-  if (my_t == NONCONV) {
-    const uint32_t slot = atomicAdd(a.nc_count, 1u);
+  if (queue) {
     a.nc_chunk[slot] = (uint32_t)c;
     a.nc_slot[c] = slot;
   }
@@ -363,11 +379,13 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
       fixed = true;
       fixed_total += out_cnt[j];
     }
+    // the first chunk of every tile goes to the fix-up kernel without a list
+    // entry (its symbols before the converging point are kept for it); the
+    // others only when their join could not be done here
+    const bool to_fix = valid[j] && !fixed && lane > 0;
+    const uint32_t fix_at = wave_append(a.fix_count, to_fix);
     if (valid[j]) {
-      // the first chunk of every tile goes to the fix-up kernel without a list
-      // entry (its symbols before the converging point are kept for it); the
-      // others only when their join could not be done here
-      if (!fixed && lane > 0) a.fix_list[atomicAdd(a.fix_count, 1u)] = (uint32_t)c[j];
+      if (to_fix) a.fix_list[fix_at] = (uint32_t)c[j];
       else if (fixed && a.chunk_cnt) a.chunk_cnt[c[j]] = out_cnt[j];
       if (lane == 0 && conv[j]) {
         uint64_t sy0, sy1, rs;

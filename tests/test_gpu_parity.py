@@ -182,6 +182,53 @@ def test_tables_and_nonconverging(coex):
         assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
 
 
+def test_join_levels(coex):
+    # enough non-converged chunks for one, two and three composed levels of
+    # the join (64, 4,096 and 262,144 maps per level): the parity automaton
+    # (no synchronising word) and random tables, byte and 2-bit input
+    n = 1_500_007
+    seq = synth.markov_bytes(27, n, with_n=True)
+    seq[100_000:100_050] = ord("N")
+    s = dev_bytes(coex, seq)
+    s2 = dev_2bit(coex, seq)[0]
+    tables = [(_parity_table(), 1)] + [(synth.random_table(seed, 12 + 9 * seed, 2), 2) for seed in (40, 41)]
+    for (dl, q0, off, ids), P in tables:
+        d = coex.Dfa.table(dl, q0, off, ids, P)
+        t = oracle.make_table(dl, q0, off, ids, P)
+        ec = oracle.scan_table(t, oracle.byte_seq(seq))[0]
+        for chunk in [8, 64, 512, 40_000]:
+            say("join levels", dl.size // 4, chunk)
+            assert gpu_counts(coex, d, s, chunk=chunk).tolist() == ec.tolist()
+            assert gpu_counts(coex, d, s2, chunk=chunk, step=1).tolist() == ec.tolist()
+        init, last, cnt = coex.count_chunks(d, s, 64)
+        e, c0 = oracle.run_range(t, oracle.byte_seq(seq), 0, 64 * 700, t.q0)
+        assert int(init.cpu().numpy()[0]) == t.q0
+        assert int(last.cpu().numpy()[699]) == e
+        assert cnt.cpu().numpy()[:700].sum(axis=0).tolist() == c0.tolist()
+
+
+def test_join_wide_lists_and_inexact_counts(coex):
+    # non-converged chunks of automata whose candidate lists are wider than a
+    # join map row (more than 64 states: the join walks each run of them in
+    # order), of one past the two-symbol limit (1,100 states: one-symbol
+    # candidate runs) and of one with up to 20 patterns per state (two-symbol
+    # entries cannot count exactly: one-symbol candidate runs)
+    n = 300_007
+    seq = synth.markov_bytes(28, n, with_n=True)
+    s = dev_bytes(coex, seq)
+    s2 = dev_2bit(coex, seq)[0]
+    tables = [(synth.random_table(42, 300, 3), 3, 1), (synth.random_table(43, 1100, 2), 2, 0),
+              (synth.random_table(44, 50, 30, accept_frac=0.3, max_out=20), 30, 0)]
+    for (dl, q0, off, ids), P, lookback in tables:
+        d = coex.Dfa.table(dl, q0, off, ids, P)
+        t = oracle.make_table(dl, q0, off, ids, P)
+        ec = oracle.scan_table(t, oracle.byte_seq(seq))[0]
+        for chunk in [512, 9_999]:
+            say("wide lists", dl.size // 4, chunk)
+            assert gpu_counts(coex, d, s, chunk=chunk, lookback=lookback).tolist() == ec.tolist()
+            assert gpu_counts(coex, d, s2, chunk=chunk, lookback=lookback).tolist() == ec.tolist()
+
+
 def test_count_chunks_records(coex):
     n = 50_000
     seq = synth.markov_bytes(25, n, with_n=True)
@@ -281,6 +328,29 @@ def test_full_genome(coex):
     assert got2.tolist() == expect.tolist()
     assert got32.tolist() == expect.tolist()
     assert got22.tolist() == expect.tolist()
+    del s
+    torch.cuda.empty_cache()
+
+
+def test_parity_automaton_genome(coex):
+    # the 3.2e9-base workload through the parity automaton, which has no
+    # synchronising word: no chunk converges, every chunk's map is built and
+    # the join composes about half a million maps; the oracle runs the whole
+    # sequence from q0
+    import torch
+    packed, mask, _ = configs.genome()
+    n = configs.GENOME_N
+    say("parity genome: generated")
+    dl, q0, off, ids = _parity_table()
+    d = coex.Dfa.table(dl, q0, off, ids, 1)
+    s = coex.to_device(packed, n=n, encoding=coex.ENC_2BIT, nmask=mask)
+    got = gpu_counts(coex, d, s)
+    got1 = gpu_counts(coex, d, s, step=1, chunk=1 << 16)
+    say("parity genome: gpu done", got.tolist(), got1.tolist())
+    expect = oracle.scan_table(oracle.make_table(dl, q0, off, ids, 1), oracle.twobit_seq(packed, mask, n))[0]
+    say("parity genome: oracle done", expect.tolist())
+    assert got.tolist() == expect.tolist()
+    assert got1.tolist() == expect.tolist()
     del s
     torch.cuda.empty_cache()
 
