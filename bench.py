@@ -518,6 +518,9 @@ def main():
     ms_step = ev0.elapsed_time(ev1) / args.steps
     k_ms, k_n = coex.profile(reset=True)
     k_avg_ms = k_ms / max(1, k_n)
+    # the kernels' own consistency checks over every step run so far (read
+    # after the timed region)
+    device_failures = coex.errors()
     gpu_counts = out[: info.n_patterns].cpu().numpy().view(np.uint64)
     value = w["n"] / (ms_step * 1e-3) / 1e9
     log("wall %.3f s for %d steps; events %.3f ms/step; scan kernel %.3f ms avg over %d launches"
@@ -547,6 +550,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
+        "device_check_failures": device_failures,
         "config": {"workload": w["desc"], "bases": w["n"], "automaton_states": info.n_states,
                    "patterns": info.n_patterns, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_tail", "achieved": round(achieved, 1),

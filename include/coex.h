@@ -67,14 +67,21 @@ extern "C" {
 
 typedef struct coex_dfa coex_dfa;
 
-/* A sequence resident in device memory.  `bases` (and `n_mask`) must be
-   16-byte aligned.  n_mask may be NULL for COEX_ENC_2BIT (no N) and is
-   ignored for COEX_ENC_BYTE. */
+/* A sequence resident in device memory (the text T[1..n] of Section II).
+   The sequence is the n_bases bases that follow the first `first_base` bases
+   of the buffers; positions reported for it count from its own first base.
+   COEX_ENC_BYTE: `bases` may have any address (a sequence that starts after a
+   FASTA header line, say); the scans read from the 16-byte boundary at or
+   below it.  COEX_ENC_2BIT: `bases` and `n_mask` must be 16-byte aligned;
+   first_base selects the starting base (any value).  n_mask may be NULL for
+   COEX_ENC_2BIT (no N) and is ignored for COEX_ENC_BYTE.  Batches
+   (coex_batch_*) take 16-byte aligned buffers with first_base = 0. */
 typedef struct {
   const void* bases;
   const uint8_t* n_mask;
   uint64_t n_bases;
   int32_t encoding;
+  uint64_t first_base;
 } coex_seq;
 
 /* Scan options; 0 in any field lets the planner choose.
@@ -161,7 +168,11 @@ void coex_dfa_free(coex_dfa* dfa);
 /* Per-pattern match counts of `dfa` over `seq` (Section III, Algorithm 1:
    chunks, possible starting states, converging point, join, fix-up).
    counts_dev: uint64[n_patterns] device buffer, overwritten.
-   Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EDEVICE. */
+   Asynchronous on `stream`.  The kernels check their own consistency (every
+   recount reaches the state the scan found, every true first state is a
+   candidate); with COEX_FLAG_CHECK the call waits and returns EINTERNAL on a
+   failure, without it the failure is kept for coex_errors_async.
+   Errors: EINVAL, ENOMEM, EDEVICE. */
 int coex_count(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, const coex_opts* opts,
                void* stream);
 
@@ -171,7 +182,9 @@ int coex_count(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, c
    hipMalloc, hipFree or other allocating call: its scratch (per-chunk
    converging points, states and counts, the fix-up list and, for automata
    that can leave a chunk unconverged, the candidate maps) lives in one static
-   device array of 64 MiB per GPU, held from library load to process exit.
+   device array of 64 MiB per GPU (its last 256 bytes keep the calls'
+   consistency failures for coex_errors_async), held from library load to
+   process exit.
    That covers every planner-chosen chunking of an automaton whose chunks
    always converge (about 36 bytes per chunk); a call whose plan needs more
    returns ESCRATCH before launching anything.  Device counters are cleared by
@@ -207,6 +220,17 @@ int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32
    counts_dev: uint64[n_chunks * n_patterns].  Asynchronous. */
 int coex_count_chunks(const coex_dfa* dfa, const coex_seq* seq, uint32_t chunk, uint32_t* init_dev,
                       uint32_t* last_dev, uint64_t* counts_dev, void* stream);
+
+/* Device consistency failures of unchecked calls, without waiting: enqueues
+   on `stream` one kernel that writes to *flags_out (device memory or mapped
+   pinned host memory, 4 bytes) the OR of the failure bits kept for the calls
+   made so far on `stream` (coex_count, coex_find, coex_count_chunks) and for
+   coex_count_noalloc calls on the current device, then clears them.  The
+   value is there once the stream reaches the kernel; 0 means every check
+   passed, any other value that some call's result is not to be trusted (the
+   bits name the check, for diagnosis).  Allocates nothing.  Errors: EINVAL
+   (flags_out NULL), EDEVICE. */
+int coex_errors_async(void* stream, uint32_t* flags_out);
 
 /* The paper's own method on the host's cores (Section III, Algorithm 1), a
    CPU baseline reported beside the GPU scan (never used by the calls above):

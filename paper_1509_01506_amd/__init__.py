@@ -29,7 +29,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -
 
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_count_noalloc", "coex_find",
-            "coex_count_chunks", "coex_count_host",
+            "coex_count_chunks", "coex_count_host", "coex_errors_async",
             "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
             "coex_batch_update", "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free",
             "coex_server_create", "coex_server_submit", "coex_server_wait", "coex_server_stats", "coex_server_free",
@@ -46,7 +46,7 @@ class CoexError(RuntimeError):
 
 class _Seq(ctypes.Structure):
     _fields_ = [("bases", ctypes.c_void_p), ("n_mask", ctypes.c_void_p), ("n_bases", ctypes.c_uint64),
-                ("encoding", ctypes.c_int32)]
+                ("encoding", ctypes.c_int32), ("first_base", ctypes.c_uint64)]
 
 
 class _Opts(ctypes.Structure):
@@ -110,6 +110,7 @@ def _lib():
         L.coex_dfa_free.restype = None
         L.coex_count.argtypes = [p, p, p, p, p]
         L.coex_count_noalloc.argtypes = [p, p, p, p, p]
+        L.coex_errors_async.argtypes = [p, p]
         L.coex_count_host.argtypes = [p, p, p, u64, ctypes.c_int32, u32, u64, u64, p]
         L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
         L.coex_count_chunks.argtypes = [p, p, u32, p, p, p, p]
@@ -235,10 +236,25 @@ class DeviceSeq:
     n: int
     encoding: int = ENC_BYTE
     nmask: "object" = None    # torch.uint8 CUDA tensor or None
+    first: int = 0            # bases of the buffers before the sequence's first base
+    byte_offset: int = 0      # bytes added to the base pointer (byte encoding: any address)
 
     def _c(self) -> _Seq:
-        return _Seq(self.bases.data_ptr() if self.n else 0,
-                    self.nmask.data_ptr() if self.nmask is not None else 0, self.n, self.encoding)
+        return _Seq(self.bases.data_ptr() + self.byte_offset if self.n else 0,
+                    self.nmask.data_ptr() if self.nmask is not None else 0, self.n, self.encoding, self.first)
+
+    def sub(self, start: int, n: Optional[int] = None, by_address: bool = False) -> "DeviceSeq":
+        """The n bases from `start` of this sequence (to its end by default),
+        sharing its buffers: by first_base, or for byte sequences by moving
+        the base pointer itself to that byte (any address)."""
+        n = self.n - start if n is None else n
+        if start < 0 or n < 0 or start + n > self.n:
+            raise ValueError("sub-sequence out of range")
+        if by_address:
+            if self.encoding != ENC_BYTE:
+                raise ValueError("by_address needs the byte encoding")
+            return DeviceSeq(self.bases, n, self.encoding, self.nmask, self.first, self.byte_offset + start)
+        return DeviceSeq(self.bases, n, self.encoding, self.nmask, self.first + start, self.byte_offset)
 
 
 def _pad16(arr: np.ndarray) -> np.ndarray:
@@ -346,6 +362,27 @@ def count_host(dfa: Dfa, data: np.ndarray, n: Optional[int] = None, encoding: in
                                   m.ctypes.data if m is not None else None, int(n), int(encoding), int(threads),
                                   int(chunks), int(window), out.ctypes.data), "count_host")
     return out[:dfa.info().n_patterns]
+
+
+def errors_async(out, stream=None):
+    """Enqueues on the stream the read-and-clear of the device consistency
+    failures kept since the last read (0 = every check passed): `out` is an
+    int32 tensor (device, or pinned host memory) whose first element receives
+    them once the stream gets there."""
+    _check(_lib().coex_errors_async(_stream(stream), out.data_ptr()), "errors_async")
+    return out
+
+
+def errors(stream=None) -> int:
+    """errors_async into pinned host memory, then a wait for the stream."""
+    import torch
+    out = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+    errors_async(out, stream)
+    if stream is None or isinstance(stream, int):
+        torch.cuda.synchronize()
+    else:
+        stream.synchronize()
+    return int(out[0])
 
 
 def count_chunks(dfa: Dfa, seq: DeviceSeq, chunk: int, stream=None):

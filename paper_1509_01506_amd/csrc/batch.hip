@@ -1011,7 +1011,7 @@ int set_work(Batch& B, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pai
     if (enc < 0) enc = e;
     else if (enc != e) return COEX_EINVAL;
     if (q.n_bases > 0 && !q.bases) return COEX_EINVAL;
-    if (((uintptr_t)q.bases & 15) || ((uintptr_t)q.n_mask & 15)) return COEX_EINVAL;
+    if (((uintptr_t)q.bases & 15) || ((uintptr_t)q.n_mask & 15) || q.first_base) return COEX_EINVAL;
     sv[s] = SeqD{reinterpret_cast<const uint8_t*>(q.bases), e == 1 ? q.n_mask : nullptr, q.n_bases};
   }
   std::vector<uint32_t> ps, pd;

@@ -46,9 +46,18 @@ namespace coex {
 constexpr uint32_t kSmallSortKeys = 4096;
 size_t sort_temp_bytes(uint64_t cap);
 int sort_match_keys(const uint64_t* keys, uint64_t* tmp, uint64_t n, void* temp, size_t temp_bytes, int64_t* pos,
-                    uint32_t* pat, hipStream_t st);
+                    uint32_t* pat, uint64_t first, hipStream_t st);
 
 // ====================================================================== kernels
+// The kept failure words of a stream's calls and of the no-allocation calls,
+// OR-ed into *out (device or host-mapped memory) and cleared.
+__global__ void k_take_errors(uint32_t* ws, uint32_t* st, uint32_t* out) {
+  if (threadIdx.x != 0) return;
+  uint32_t e = atomicExch(st, 0u);
+  if (ws) e |= atomicExch(ws, 0u);
+  *out = e;
+}
+
 __global__ void k_init(ScanArgs a, uint64_t* counts, uint32_t n_counts) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
@@ -88,7 +97,7 @@ __global__ __launch_bounds__(256) void k_nonconv(ScanArgs a) {
   if (STEP == 2) copy_to_lds(lds, a.T2, a.n_states * 64u);
   copy_to_lds(lds + t1_at, a.T1, a.n_states * 16u);
   __syncthreads();
-  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
+  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) flag_error(a, 64u);
   const Tab tb{STEP == 2 ? lds : nullptr, lds + t1_at, a.q0s};
   const uint32_t G = a.nc_group;
   const uint64_t n_pairs = (uint64_t)*a.nc_count * G;
@@ -101,7 +110,7 @@ __global__ __launch_bounds__(256) void k_nonconv(ScanArgs a) {
     const uint32_t slot = in ? (uint32_t)(pair / G) : 0u;
     const uint32_t i = (uint32_t)(pair % G);
     const uint64_t c = in ? a.nc_chunk[slot] : 0;
-    const uint64_t lo = c * a.chunk;
+    const uint64_t lo = chunk_lo(a, c);
     const uint64_t hi = in ? (lo + a.chunk < a.n ? lo + a.chunk : a.n) : 0;
     uint32_t m = 0, cbase = 0, exact = 0;
     bool is_exact = false;
@@ -168,7 +177,7 @@ __device__ __forceinline__ uint32_t find_cand(const ScanArgs& a, uint32_t slot, 
   const uint32_t m = a.nc_m[slot];
   for (uint32_t i = 0; i < m; ++i)
     if (cand[i] == state) return i;
-  atomicOr(a.err, 1u);  // the true first state is always a candidate
+  flag_error(a, 1u);  // the true first state is always a candidate
   return 0;
 }
 
@@ -322,7 +331,7 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
   uint64_t mine_sum = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_fix; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t c = i < n_imp ? i * TILE : a.fix_list[i - n_imp];
-    const uint64_t lo = c * a.chunk;
+    const uint64_t lo = chunk_lo(a, c);
     const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     SinkGlobal sink{a.wtab, a.acc_out_off, a.acc_out_ids, per_state ? a.pat_counts : nullptr, a.app_count, a.app_keys,
                     a.app_cap};
@@ -332,17 +341,17 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
     uint64_t mine;
     const uint32_t ct = a.conv_t[c];
     if (direct && ct == NONCONV) {
-      atomicOr(a.err, 128u);
+      flag_error(a, 128u);
       mine = 0;
     } else if (ct == NONCONV && !per_state && !a.app_count) {
       // a weighted total only: the candidate runs counted the chunk
       const uint32_t slot = a.nc_slot[c];
       const uint64_t at = (uint64_t)slot * a.max_cand + find_cand(a, slot, s0);
-      if (a.nc_end[at] != a.true_start[c + 1]) atomicOr(a.err, 2u);
+      if (a.nc_end[at] != a.true_start[c + 1]) flag_error(a, 2u);
       mine = a.nc_cnt[at];
     } else if (ct == NONCONV) {
       const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
-      if (e != a.true_start[c + 1]) atomicOr(a.err, 2u);
+      if (e != a.true_start[c + 1]) flag_error(a, 2u);
       mine = sink.cnt;
     } else {
       uint32_t e;
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(256) void k_fixup(ScanArgs a, int per_state, int di
       } else {
         e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, lo + ct, sink);
       }
-      if (e != a.conv_s[c]) atomicOr(a.err, 4u);
+      if (e != a.conv_s[c]) flag_error(a, 4u);
       mine = (uint64_t)sink.cnt + a.tail_cnt[c];
     }
     if (a.chunk_cnt) a.chunk_cnt[c] = mine;
@@ -413,16 +422,16 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(ScanArgs a) {
   copy_to_lds(lds + a.lds_t1_off, a.T1, a.n_states * 16u);
   __syncthreads();
   const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
-  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
+  if (STEP == 2 && threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) flag_error(a, 64u);
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n_chunks) return;
-  const uint64_t lo = c * a.chunk;
+  const uint64_t lo = chunk_lo(a, c);
   const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
   const uint32_t s0 = a.true_start[c];
   if (MODE == 0) {
-    SinkPositions sink{a.acc_out_off, a.acc_out_ids, a.pos_out, a.pat_out, a.chunk_off[c], a.pos_cap};
+    SinkPositions sink{a.acc_out_off, a.acc_out_ids, a.pos_out, a.pat_out, a.chunk_off[c], a.pos_cap, a.first};
     scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
-    if (sink.cnt != a.chunk_cnt[c]) atomicOr(a.err, 8u);
+    if (sink.cnt != a.chunk_cnt[c]) flag_error(a, 8u);
   } else {
     uint64_t* row = a.rec_counts + c * a.n_patterns;
     for (uint32_t p = 0; p < a.n_patterns; ++p) row[p] = 0;
@@ -430,7 +439,7 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(ScanArgs a) {
     const uint32_t e = scan_range<ENC, SHIFT, STEP>(a, tb, s0, lo, hi, sink);
     a.rec_init[c] = s0 >> a.shift;
     a.rec_last[c] = e >> a.shift;
-    if (e != a.true_start[c + 1]) atomicOr(a.err, 16u);
+    if (e != a.true_start[c + 1]) flag_error(a, 16u);
   }
 }
 
@@ -441,6 +450,9 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(ScanArgs a) {
 // address): the address comes from hipGetSymbolAddress, once per device.
 constexpr size_t kStaticScratchBytes = 64ull << 20;
 static __device__ __align__(256) char scratch[kStaticScratchBytes];
+// The last 256 bytes of the array hold the failure word kept across
+// coex_count_noalloc calls (zero at load, cleared when read).
+constexpr size_t kStaticStickyAt = kStaticScratchBytes - 256;
 
 struct DeviceCopy {
   int device = -1;
@@ -480,6 +492,7 @@ struct Workspace {
   char* buf = nullptr;
   size_t bytes = 0;
   int device = -1;
+  uint32_t* sticky = nullptr;  // failures of this stream's calls, kept until coex_errors_async reads them
   // event pairs around the scan kernel of calls made with COEX_FLAG_TIME
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   size_t ev_used = 0;
@@ -663,6 +676,10 @@ int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) 
   std::lock_guard<std::mutex> lk(g_mu);
   Workspace& w = g_ws[{dev, stream}];
   wsp = &w;
+  if (!w.sticky) {
+    if (hipMalloc(&w.sticky, 256) != hipSuccess) { w.sticky = nullptr; return COEX_ENOMEM; }
+    if (hipMemset(w.sticky, 0, 256) != hipSuccess) return COEX_EDEVICE;
+  }
   if (w.bytes < bytes) {
     if (w.buf) {
       if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return COEX_EDEVICE;
@@ -954,7 +971,27 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   Dfa& d = *const_cast<Dfa*>(reinterpret_cast<const Dfa*>(h));
   if (seq->encoding != COEX_ENC_BYTE && seq->encoding != COEX_ENC_2BIT) return COEX_EINVAL;
   if (seq->n_bases > 0 && !seq->bases) return COEX_EINVAL;
-  if (((uintptr_t)seq->bases & 15) || ((uintptr_t)seq->n_mask & 15)) return COEX_EINVAL;
+  // where the sequence starts: byte sequences may start at any address (the
+  // kernels read from the 16-byte boundary below it and skip the bases in
+  // front); 2-bit buffers are 16-byte aligned and first_base picks the base.
+  // Whole 128-base steps move the pointers (16-byte steps of codes and mask).
+  const uint8_t* bases = static_cast<const uint8_t*>(seq->bases);
+  const uint8_t* nmask = seq->encoding == COEX_ENC_2BIT ? seq->n_mask : nullptr;
+  uint64_t first = seq->first_base;
+  if (seq->encoding == COEX_ENC_BYTE) {
+    const uintptr_t mis = (uintptr_t)bases & 15u;
+    bases -= mis;
+    first += mis;
+  } else if (((uintptr_t)bases & 15u) || ((uintptr_t)nmask & 15u)) {
+    return COEX_EINVAL;
+  }
+  if (first >= (1ull << 62) || seq->n_bases >= (1ull << 62)) return COEX_EINVAL;
+  {
+    const uint64_t skip = first & ~127ull;
+    if (bases) bases += seq->encoding == COEX_ENC_BYTE ? skip : skip / 4;
+    if (nmask) nmask += skip / 8;
+    first -= skip;
+  }
   if (hipGetDevice(&C.dev) != hipSuccess) return COEX_EDEVICE;
   int rc = dev_props(C.dev, C.n_cu);
   if (rc) return rc;
@@ -1026,7 +1063,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   size_t o_cc = need_chunk_cnt ? take(nc * 8) : 0, o_co = need_chunk_cnt ? take(nc * 8) : 0;
   size_t o_part = need_chunk_cnt ? take((nc + kCountTile - 1) / kCountTile * 8) : 0;
   if (noalloc) {
-    if (off > kStaticScratchBytes) return COEX_ESCRATCH;
+    if (off > kStaticStickyAt) return COEX_ESCRATCH;
     rc = static_scratch(C.dev, C.ws);
     C.wsp = nullptr;
   } else {
@@ -1037,9 +1074,10 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   C.timed = o && (o->flags & COEX_FLAG_TIME);
   ScanArgs& a = C.a;
   char* w = C.ws;
-  a.bases = reinterpret_cast<const uint8_t*>(seq->bases);
-  a.nmask = seq->encoding == COEX_ENC_2BIT ? seq->n_mask : nullptr;
-  a.n = seq->n_bases;
+  a.bases = bases;
+  a.nmask = nmask;
+  a.first = first;
+  a.n = first + seq->n_bases;
   a.chunk = P.chunk;
   a.n_chunks = P.n_chunks;
   a.n_tiles = P.n_tiles;
@@ -1095,6 +1133,7 @@ int prepare(const coex_dfa* h, const coex_seq* seq, const coex_opts* o, void* st
   a.true_start = reinterpret_cast<uint32_t*>(w + o_ts);
   a.total = reinterpret_cast<unsigned long long*>(w + o_tot);
   a.err = reinterpret_cast<uint32_t*>(w + o_err);
+  a.err_sticky = noalloc ? reinterpret_cast<uint32_t*>(w + kStaticStickyAt) : C.wsp->sticky;
   a.app_count = positions ? reinterpret_cast<unsigned long long*>(w + o_app) : nullptr;
   a.app_keys = nullptr;
   a.app_cap = 0;
@@ -1269,6 +1308,23 @@ int coex_count_noalloc(const coex_dfa* dfa, const coex_seq* seq, uint64_t* count
   }
 }
 
+int coex_errors_async(void* stream, uint32_t* flags_out) {
+  if (!flags_out) return COEX_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return COEX_EDEVICE;
+  uint32_t* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(coex::g_mu);
+    auto it = coex::g_ws.find({dev, stream});
+    if (it != coex::g_ws.end()) ws = it->second.sticky;
+  }
+  char* sp = nullptr;
+  if (coex::static_scratch(dev, sp) != COEX_OK) return COEX_EDEVICE;
+  hipLaunchKernelGGL(coex::k_take_errors, dim3(1), dim3(64), 0, (hipStream_t)stream, ws,
+                     reinterpret_cast<uint32_t*>(sp + coex::kStaticStickyAt), flags_out);
+  return hipGetLastError() == hipSuccess ? COEX_OK : COEX_EDEVICE;
+}
+
 }  // extern "C"
 
 namespace coex {
@@ -1307,7 +1363,8 @@ int find_one_pass(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, ui
     if (rc) return rc;
   }
   if (sort_match_keys(reinterpret_cast<const uint64_t*>(pos_dev), reinterpret_cast<uint64_t*>(tmp), total,
-                      tmp ? tmp + align_up(total * 8, 256) : nullptr, temp_bytes, pos_dev, pattern_dev, C.st))
+                      tmp ? tmp + align_up(total * 8, 256) : nullptr, temp_bytes, pos_dev, pattern_dev, C.a.first,
+                      C.st))
     return COEX_EDEVICE;
   return COEX_OK;
 }
@@ -1355,7 +1412,7 @@ int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32
   if (!dfa || !seq) return COEX_EINVAL;
   try {
     const Dfa& d = *reinterpret_cast<const Dfa*>(dfa);
-    const bool one_pass = d.n_patterns <= (1u << 24) && seq->n_bases < (1ull << 40) && (!opts || opts->chains <= 1);
+    const bool one_pass = d.n_patterns <= (1u << 24) && seq->n_bases < (1ull << 40) - 256 && (!opts || opts->chains <= 1);
     return one_pass ? coex::find_one_pass(dfa, seq, pos_dev, pattern_dev, capacity, n_found, opts, stream)
                     : coex::find_two_pass(dfa, seq, pos_dev, pattern_dev, capacity, n_found, opts, stream);
   } catch (const std::bad_alloc&) {

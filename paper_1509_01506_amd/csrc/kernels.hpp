@@ -57,7 +57,8 @@ struct ScanArgs {
   // sequence
   const uint8_t* bases;
   const uint8_t* nmask;
-  uint64_t n;
+  uint64_t n;                 // buffer position one past the sequence's last base
+  uint64_t first;             // buffer position of the sequence's first base
   uint64_t chunk;
   uint64_t n_chunks;
   uint64_t n_tiles;
@@ -104,6 +105,7 @@ struct ScanArgs {
   unsigned long long* total;  // weighted total
   uint64_t* chunk_cnt;        // per chunk total (find / records)
   uint32_t* err;              // device consistency flag
+  uint32_t* err_sticky;       // failures kept across calls until read (coex_errors_async), or NULL
   // outputs per accepting index
   const uint32_t* acc_out_off;
   const uint32_t* acc_out_ids;
@@ -122,6 +124,13 @@ struct ScanArgs {
   uint64_t* app_keys;
   uint64_t app_cap;
 };
+
+// A failed device consistency check: the call's own word (read by checked
+// calls) and the word kept until the caller reads it.
+__device__ __forceinline__ void flag_error(const ScanArgs& a, uint32_t bits) {
+  atomicOr(a.err, bits);
+  if (a.err_sticky) atomicOr(a.err_sticky, bits);
+}
 
 // ------------------------------------------------------------------ symbols
 // Column of the base at p for the table of encoding ENC, or -1 for a reset.
@@ -251,12 +260,13 @@ struct SinkPositions {  // end positions and pattern ids, in order
   uint32_t* pat;
   uint64_t at;
   uint64_t cap;              // writes stop at the buffer end whatever the count
+  uint64_t first;            // buffer position of the sequence's first base
   uint32_t cnt = 0;
   __device__ void word(uint32_t) {}
   __device__ void hit(uint64_t p, uint32_t a) {
     for (uint32_t i = out_off[a]; i < out_off[a + 1]; ++i) {
       if (at < cap) {
-        pos[at] = (int64_t)p;
+        pos[at] = (int64_t)(p - first);
         if (pat) pat[at] = out_ids[i];
       }
       ++at;
@@ -819,6 +829,10 @@ __device__ __forceinline__ void lookback8(const ScanArgs& a, uint64_t lo, uint32
   }
 }
 
+// First base of chunk c (buffer position): chunks are counted from the
+// sequence's first base.
+__device__ __forceinline__ uint64_t chunk_lo(const ScanArgs& a, uint64_t c) { return a.first + c * a.chunk; }
+
 // Candidate list of the chunk starting at lo: either one exact state (chunk
 // 0, a reset inside the lookback window, or a window that reaches the
 // sequence start) or the PSS table entry of the k-gram before the chunk.
@@ -829,11 +843,11 @@ __device__ __forceinline__ void chunk_header(const ScanArgs& a, const Tab& tb, c
   cbase = 0;
   exact = tb.q0s;
   is_exact = true;
-  if (lo == 0) return;
+  if (lo == a.first) return;
   const uint32_t k = a.k;
-  if (lo < 8) {  // the window reaches the sequence start: run from q0
+  if (lo - a.first < 8) {  // the window reaches the sequence start: run from q0
     uint32_t s = tb.q0s;
-    for (uint64_t i = 0; i < lo; ++i) {
+    for (uint64_t i = a.first; i < lo; ++i) {
       const int col = load_col<ENC>(a, i);
       s = col < 0 ? tb.q0s : (t1_lookup<SHIFT>(tb, s, (uint32_t)col) & 0xFFFFu);
     }

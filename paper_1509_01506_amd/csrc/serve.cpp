@@ -300,7 +300,7 @@ bool launch(coex_server* S) {
   std::vector<coex_seq> seqs(n);
   std::vector<uint32_t> ps(n), pd(n);
   for (uint32_t i = 0; i < n; ++i) {
-    seqs[i] = coex_seq{S->arena.base + ready[i]->off, nullptr, ready[i]->n, COEX_ENC_BYTE};
+    seqs[i] = coex_seq{S->arena.base + ready[i]->off, nullptr, ready[i]->n, COEX_ENC_BYTE, 0};
     ps[i] = i;
     pd[i] = ready[i]->dfa;
   }

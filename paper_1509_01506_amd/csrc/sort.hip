@@ -15,8 +15,10 @@ namespace coex {
 constexpr uint32_t kSmallSort = 4096;
 
 // One block of 1024 threads: bitonic sort of n <= kSmallSort keys in LDS
-// (padded with ~0), then the split into positions and pattern ids.
-__global__ __launch_bounds__(1024) void k_sort_small(const uint64_t* keys, uint64_t n, int64_t* pos, uint32_t* pat) {
+// (padded with ~0), then the split into positions (counted from the
+// sequence's first base, buffer position `first`) and pattern ids.
+__global__ __launch_bounds__(1024) void k_sort_small(const uint64_t* keys, uint64_t n, int64_t* pos, uint32_t* pat,
+                                                     uint64_t first) {
   __shared__ uint64_t k[kSmallSort];
   uint32_t m = 1;
   while (m < n) m <<= 1;
@@ -38,14 +40,14 @@ __global__ __launch_bounds__(1024) void k_sort_small(const uint64_t* keys, uint6
       __syncthreads();
     }
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    pos[i] = (int64_t)(k[i] >> 24);
+    pos[i] = (int64_t)((k[i] >> 24) - first);
     if (pat) pat[i] = (uint32_t)(k[i] & 0xFFFFFFu);
   }
 }
 
-__global__ void k_split_keys(const uint64_t* keys, uint64_t n, int64_t* pos, uint32_t* pat) {
+__global__ void k_split_keys(const uint64_t* keys, uint64_t n, int64_t* pos, uint32_t* pat, uint64_t first) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    pos[i] = (int64_t)(keys[i] >> 24);
+    pos[i] = (int64_t)((keys[i] >> 24) - first);
     if (pat) pat[i] = (uint32_t)(keys[i] & 0xFFFFFFu);
   }
 }
@@ -61,18 +63,20 @@ size_t sort_temp_bytes(uint64_t cap) {
 }
 
 // keys[0..n) -> pos/pat in order; `tmp` holds n keys, `temp` the sort's
-// temporary storage (sort_temp_bytes(cap) bytes, cap >= n).  Asynchronous.
+// temporary storage (sort_temp_bytes(cap) bytes, cap >= n); key positions
+// are buffer positions, `first` the one of the sequence's first base.
+// Asynchronous.
 int sort_match_keys(const uint64_t* keys, uint64_t* tmp, uint64_t n, void* temp, size_t temp_bytes, int64_t* pos,
-                    uint32_t* pat, hipStream_t st) {
+                    uint32_t* pat, uint64_t first, hipStream_t st) {
   if (n == 0) return 0;
   if (n <= kSmallSort) {
-    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, st, keys, n, pos, pat);
+    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, st, keys, n, pos, pat, first);
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
   size_t bytes = temp_bytes;
   if (rocprim::radix_sort_keys(temp, bytes, keys, tmp, (size_t)n, 0, 64, st) != hipSuccess) return -1;
   const uint32_t blocks = (uint32_t)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
-  hipLaunchKernelGGL(k_split_keys, dim3(blocks), dim3(256), 0, st, tmp, n, pos, pat);
+  hipLaunchKernelGGL(k_split_keys, dim3(blocks), dim3(256), 0, st, tmp, n, pos, pat, first);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

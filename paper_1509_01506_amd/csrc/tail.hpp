@@ -114,7 +114,7 @@ __device__ __forceinline__ void spec_tile(const ScanArgs& a, const Tab& tb, cons
   const int lane = threadIdx.x & 63;
   const uint64_t c = tile_id * TILE + lane;
   const bool valid = c < a.n_chunks;
-  const uint64_t lo = valid ? c * a.chunk : 0;
+  const uint64_t lo = valid ? chunk_lo(a, c) : 0;
   const uint64_t hi = valid ? (lo + a.chunk < a.n ? lo + a.chunk : a.n) : 0;
   uint32_t m = 0, cbase = 0, exact = 0;
   bool is_exact = false;
@@ -316,7 +316,7 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
   }
   __syncthreads();
   const Tab tb{lds, lds + a.lds_t1_off, a.q0s};
-  if (threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) atomicOr(a.err, 64u);
+  if (threadIdx.x == 0 && (uint32_t)(uintptr_t)(lds_c*)lds != 0u) flag_error(a, 64u);
   using Sink = SinkTail<MODE>;
   const Sink sink0{a.lds_t1_off, a.q0s, a.lds_w_off, a.lds_hist_off,
                    AppendTo{a.acc_out_off, a.acc_out_ids, a.app_count, a.app_keys, a.app_cap}};
@@ -335,7 +335,7 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
     valid[j] = c[j] < a.n_chunks;
     if (!valid[j]) my_t[j] = NONCONV;
     conv[j] = my_t[j] != NONCONV;
-    lo[j] = c[j] * a.chunk;
+    lo[j] = chunk_lo(a, c[j]);
     hi[j] = valid[j] ? (lo[j] + a.chunk < a.n ? lo[j] + a.chunk : a.n) : 0;
     out_e[j] = 0;
     out_cnt[j] = 0;
@@ -374,7 +374,7 @@ __attribute__((amdgpu_waves_per_eu(TailShape<STEP, CH>::kMinWaves, 8))) void k_t
       if ((lo[j] & 63) == 0 && lo[j] + SPEC_WIN <= a.n) front_symbols<ENC>(a, lo[j], sy0, sy1, rs);
       else stage_symbols<ENC>(a, lo[j], hi[j], sy0, sy1, rs);
       const uint32_t e = run_staged<SHIFT>(tb, pe, sy0, sy1, rs, my_t[j], lo[j], sink);
-      if (e != my_s[j]) atomicOr(a.err, 32u);
+      if (e != my_s[j]) flag_error(a, 32u);
       out_cnt[j] += sink.cnt;
       fixed = true;
       fixed_total += out_cnt[j];

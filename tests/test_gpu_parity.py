@@ -229,6 +229,72 @@ def test_join_wide_lists_and_inexact_counts(coex):
             assert gpu_counts(coex, d, s2, chunk=chunk, lookback=lookback).tolist() == ec.tolist()
 
 
+def test_unaligned_starts(coex):
+    # sequences starting at any base of their buffers (the text T[1..n] wherever
+    # it lies): byte sequences by address (1..15 bytes past a 16-byte boundary,
+    # and further) and by first_base, 2-bit sequences by first_base; counts and
+    # positions of an automaton with a synchronising word and counts of one
+    # without, against the oracle on the same bases
+    n = 150_011
+    seq = synth.markov_bytes(29, n, with_n=True)
+    kmers = synth.random_kmers(30, 6, 7) + ["ACG"]
+    d = coex.Dfa.kmers(kmers)
+    dl, q0, off, ids = _parity_table()
+    dp = coex.Dfa.table(dl, q0, off, ids, 1)
+    tp = oracle.make_table(dl, q0, off, ids, 1)
+    s = dev_bytes(coex, seq)
+    s2 = dev_2bit(coex, seq)[0]
+    for start in list(range(1, 16)) + [16, 17, 127, 128, 129, 1000, 4099]:
+        m = n - start - (start % 7)
+        sub = seq[start:start + m]
+        ec, epos, epat = oracle.count_kmers(kmers, oracle.byte_seq(sub), positions=True)
+        ep = oracle.scan_table(tp, oracle.byte_seq(sub))[0]
+        views = {"address": s.sub(start, m, by_address=True), "first_base": s.sub(start, m),
+                 "2bit": s2.sub(start, m)}
+        for name, v in views.items():
+            say("unaligned", start, name)
+            assert gpu_counts(coex, d, v).tolist() == ec.tolist(), (start, name)
+            assert gpu_counts(coex, d, v, chunk=64).tolist() == ec.tolist(), (start, name)
+            assert gpu_counts(coex, dp, v, chunk=1000).tolist() == ep.tolist(), (start, name)
+            pos, pat = coex.find(d, v, chunk=4096)
+            assert pos.cpu().numpy().tolist() == epos.tolist(), (start, name)
+            assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist(), (start, name)
+        if start in (3, 129):
+            init, last, cnt = coex.count_chunks(dp, views["2bit"], 777)
+            e, c0 = oracle.run_range(tp, oracle.byte_seq(sub), 0, 777 * 5, tp.q0)
+            assert int(last.cpu().numpy()[4]) == e
+            assert cnt.cpu().numpy()[:5].sum(axis=0).tolist() == c0.tolist()
+
+
+def test_errors_async(coex):
+    # unchecked calls keep their device consistency failures until read: none
+    # after correct scans, on the current stream, another stream and the
+    # no-allocation path
+    import torch
+    seq = synth.markov_bytes(31, 100_000, with_n=True)
+    s = dev_bytes(coex, seq)
+    d = coex.Dfa.kmers(synth.random_kmers(32, 4, 8))
+    dl, q0, off, ids = _parity_table()
+    dp = coex.Dfa.table(dl, q0, off, ids, 1)
+    for _ in range(3):
+        coex.count(d, s)
+        coex.count(dp, s, chunk=512)
+        coex.find(d, s)
+    out = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    coex.errors_async(out)
+    assert int(out.cpu()[0]) == 0
+    st = torch.cuda.Stream()
+    pinned = torch.full((1,), -1, dtype=torch.int32, pin_memory=True)
+    with torch.cuda.stream(st):
+        coex.count(dp, s, stream=st)
+        coex.errors_async(pinned, stream=st)
+    st.synchronize()
+    assert int(pinned[0]) == 0
+    buf = torch.empty(4, dtype=torch.int64, device="cuda")
+    coex.count_noalloc(d, s, out=buf)
+    assert coex.errors() == 0
+
+
 def test_count_chunks_records(coex):
     n = 50_000
     seq = synth.markov_bytes(25, n, with_n=True)

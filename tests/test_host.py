@@ -47,6 +47,46 @@ def test_header_symbols_exported(coex):
     assert set(coex.EXPORTED) == names
 
 
+def test_struct_layouts_match_header(coex, tmp_path):
+    # the binding's ctypes structures against the header's, as a C compiler
+    # lays them out
+    import ctypes
+    import subprocess
+    prog = tmp_path / "layout.c"
+    prog.write_text("""#include <stddef.h>
+#include <stdio.h>
+#include "coex.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(coex_seq), offsetof(coex_seq, n_bases), offsetof(coex_seq, encoding),
+         offsetof(coex_seq, first_base), sizeof(coex_opts), offsetof(coex_opts, chains));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)])
+    got = [int(x) for x in subprocess.check_output([str(exe)], text=True).split()]
+    S, O = coex._Seq, coex._Opts
+    assert got == [ctypes.sizeof(S), S.n_bases.offset, S.encoding.offset, S.first_base.offset, ctypes.sizeof(O),
+                   O.chains.offset]
+
+
+def test_sub_sequences(coex):
+    # sub-sequence descriptors share the buffers: first_base or the pointer moves
+    import types
+    fake = types.SimpleNamespace(data_ptr=lambda: 4096)
+    s = coex.DeviceSeq(fake, 100, coex.ENC_BYTE)
+    a = s.sub(5, 90)
+    assert (a.first, a.byte_offset, a.n) == (5, 0, 90)
+    b = a.sub(3, by_address=True)
+    assert (b.first, b.byte_offset, b.n) == (5, 3, 87)
+    c = b._c()
+    assert (c.bases, c.first_base, c.n_bases) == (4099, 5, 87)
+    with pytest.raises(ValueError):
+        s.sub(50, 51)
+    with pytest.raises(ValueError):
+        coex.DeviceSeq(fake, 100, coex.ENC_2BIT).sub(1, by_address=True)
+
+
 def test_kmers_match_brute_force(coex):
     for seed in range(5):
         st = synth.Stream(seed, 77)
