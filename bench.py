@@ -196,10 +196,10 @@ def bench_batched(args, w):
     dset = coex.DfaSet(w["dfas"])
     out = torch.empty(len(seqs) * len(w["dfas"]), dtype=torch.int64, device="cuda")
     tb = coex.Batch(dset, seqs)
-    chunk = tb.tune(out=out)
+    chunk, width = tb.tune(out=out)
     tb.free()
-    b = coex.Batch(dset, seqs, chunk=chunk, graph=True, timed=True)
-    log("tuned chunk %d; %s" % (chunk, b.info()))
+    b = coex.Batch(dset, seqs, chunk=chunk, width=width, graph=True, timed=True)
+    log("tuned chunk %d, width cap %d; %s" % (chunk, width, b.info()))
     t_warm = time.perf_counter()
     while time.perf_counter() - t_warm < args.clock_warmup_s:
         b.run(out=out)
@@ -253,7 +253,8 @@ def bench_batched(args, w):
         "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": w["desc"], "bases": n, "pairs": len(seqs) * len(w["dfas"]),
-                   "chunk": info.chunk, "width": info.width, "lds_groups": groups, "parallelism": "single GPU"},
+                   "chunk": info.chunk, "width_cap": width, "width": info.width, "lds_groups": groups,
+                   "parallelism": "single GPU"},
         "base_automaton_steps_per_s": round(n * len(w["dfas"]) / (ms_step * 1e-3) / 1e12, 3),
         "plain": {"ms": round(plain_ms, 2), "gbases_per_s": round(n / (plain_ms * 1e-3) / 1e9, 2),
                   "speedup_of_batched": round(plain_ms / ms_step, 2), "spot_checks_equal": plain_ok},

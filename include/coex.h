@@ -282,7 +282,9 @@ void coex_dfa_set_free(coex_dfa_set* set);
    device-resident (16-byte aligned) and must all use one encoding; the batch
    keeps their pointers, so they must stay valid while it is run.
    opts->chunk: bases per chunk (>= 64; 0 = chosen from the batch size and
-   the GPU); flags: COEX_FLAG_CHECK, COEX_FLAG_TIME (events around the scan
+   the GPU); opts->width: width cap of this batch (a power of two up to the
+   set's; 0 = the set's; coex_batch_tune reports the fastest); flags:
+   COEX_FLAG_CHECK, COEX_FLAG_TIME (events around the scan
    kernel, or the whole graph; read by coex_batch_info), COEX_FLAG_GRAPH.
    Synchronous (uploads descriptors).  Errors: EINVAL, ENOMEM, EDEVICE. */
 int coex_batch_create(const coex_dfa_set* set, const coex_seq* seqs, uint32_t n_seq, const uint32_t* pair_seq,
@@ -299,15 +301,22 @@ int coex_batch_update(coex_batch* batch, const coex_seq* seqs, uint32_t n_seq, c
    COEX_FLAG_CHECK was given.  Runs of one batch must not overlap. */
 int coex_batch_run(coex_batch* batch, uint64_t* counts_dev, void* stream);
 
-/* Autotuner: runs the batch with chunk lengths 4 KiB, 16 KiB, ..., 1 MiB,
-   times each with HIP events (after one warm-up run each), keeps the fastest
-   and reports it in *chunk_out.  counts_dev as for coex_batch_run (holds the
-   last run's exact counts).  Synchronises `stream`. */
-int coex_batch_tune(coex_batch* batch, uint64_t* counts_dev, void* stream, uint64_t* chunk_out);
+/* Autotuner: runs the batch for every speculation width cap 1, 2, 4, ...
+   up to the set's (opts->width at coex_dfa_set_create, default 64; the cap
+   picks each automaton's lookback, and so how many possible starting states
+   its chunks speculate on; caps that pick the same lookbacks for every
+   automaton run once) crossed with chunk lengths 4 KiB, 16 KiB, ..., 1 MiB,
+   times each with HIP events (after one warm-up run each), keeps the
+   fastest pair and reports it in *chunk_out and *width_out (may be NULL).
+   counts_dev as for coex_batch_run (holds the last run's exact counts).
+   Synchronises `stream`. */
+int coex_batch_tune(coex_batch* batch, uint64_t* counts_dev, void* stream, uint64_t* chunk_out,
+                    uint32_t* width_out);
 
 typedef struct {
   uint64_t chunk;     /* bases per chunk */
-  uint32_t width;     /* largest possible-starting-state list of any automaton of the set */
+  uint32_t width;     /* largest possible-starting-state list of any automaton under the batch's
+                         width cap (the set's, or the tuner's choice) */
   uint32_t step;      /* symbols per LDS lookup: 1 or 2 (every group), 3 = groups of both kinds */
   uint32_t n_groups;  /* LDS groups of the automaton set */
   uint32_t n_pairs;

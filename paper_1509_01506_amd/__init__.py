@@ -127,7 +127,7 @@ def _lib():
         L.coex_server_stats.argtypes = [p, p]
         L.coex_server_free.argtypes = [p]
         L.coex_server_free.restype = None
-        L.coex_batch_tune.argtypes = [p, p, p, p]
+        L.coex_batch_tune.argtypes = [p, p, p, p, p]
         L.coex_batch_info.argtypes = [p, p]
         L.coex_batch_free.argtypes = [p]
         L.coex_batch_free.restype = None
@@ -465,11 +465,11 @@ class Batch:
     shaped [n_seq, n_dfa]; else a list of (seq index, dfa index), result [n]."""
 
     def __init__(self, dset: DfaSet, seqs: Sequence[DeviceSeq], pairs=None, chunk: int = 0, check: bool = False,
-                 timed: bool = False, graph: bool = False):
+                 timed: bool = False, graph: bool = False, width: int = 0):
         self.dset = dset
         self.seqs = list(seqs)          # keeps the device buffers alive
         ss = (_Seq * max(1, len(self.seqs)))(*[s._c() for s in self.seqs])
-        o = _opts(chunk=chunk, check=check, timed=timed, graph=graph)
+        o = _opts(chunk=chunk, width=width, check=check, timed=timed, graph=graph)
         out = ctypes.c_void_p()
         if pairs is None:
             self.shape = (len(self.seqs), len(dset.dfas))
@@ -504,11 +504,15 @@ class Batch:
         _check(_lib().coex_batch_run(self._h, out.data_ptr(), _stream(stream)), "batch_run")
         return out[: self.n_pairs].view(self.shape)
 
-    def tune(self, out=None, stream=None) -> int:
+    def tune(self, out=None, stream=None):
+        """Autotunes chunk length and speculation width cap together; returns
+        (chunk, width cap) and keeps them for later runs."""
         out = self._checked(self._out(out))
         c = ctypes.c_uint64(0)
-        _check(_lib().coex_batch_tune(self._h, out.data_ptr(), _stream(stream), ctypes.byref(c)), "batch_tune")
-        return int(c.value)
+        w = ctypes.c_uint32(0)
+        _check(_lib().coex_batch_tune(self._h, out.data_ptr(), _stream(stream), ctypes.byref(c), ctypes.byref(w)),
+               "batch_tune")
+        return int(c.value), int(w.value)
 
     def info(self) -> BatchInfo:
         x = _BatchInfo()

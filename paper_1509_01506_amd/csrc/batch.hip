@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -568,7 +569,14 @@ struct coex_dfa_set {
   bool any_step2 = false, any_step1 = false;
   bool may_not_converge_below = false;  // some automaton has no finite synchronising depth
   uint32_t max_sync = 0;                // largest finite synchronising depth (+ lookback)
+  uint32_t wmax = 64;                   // cap on candidate lists given at creation
   std::vector<uint32_t> n_states, group_of, k_of;
+  // per automaton: largest candidate list per lookback k, synchronising
+  // depth, and the device offsets of the PSS tables uploaded (the lookbacks
+  // some width cap up to wmax selects; SIZE_MAX where none)
+  std::vector<std::array<uint32_t, coex::kMaxLookback + 1>> pss_max;
+  std::vector<uint32_t> sync_of;
+  std::vector<std::array<size_t, coex::kMaxLookback + 1>> pss_off_at, pss_states_at;
   struct Group {
     std::vector<uint32_t> members;
     uint32_t step = 2;
@@ -589,6 +597,12 @@ struct coex_batch {
   uint64_t chunk = 0, fixed_chunk = 0;
   uint32_t n_pairs = 0, flags = 0, blocks = 0, lds_bytes = 0;
   bool needs_nc = false;
+  // width cap of this batch (the set's at creation, the tuner's after
+  // coex_batch_tune): lookback per automaton, largest candidate list,
+  // convergence bounds and the automaton descriptors they give
+  uint32_t width_cap = 0, W = 1, max_sync = 0;
+  bool may_nc = false;
+  std::vector<coex::batch::DfaD> dfa_dev;
   // host descriptors (kept to rebuild with another chunk length)
   std::vector<coex::batch::SeqD> seqs;
   std::vector<uint32_t> pair_seq, pair_dfa;
@@ -624,6 +638,19 @@ namespace batch {
 using Set = coex_dfa_set;
 using Batch = coex_batch;
 
+// Lookback of an automaton under a cap w on its candidate lists (mx[k] =
+// its largest list after k bases): the shortest whose lists fit one batch of
+// registers (8) and the cap, else the one with the fewest candidates if
+// that fits the cap; 0 if none does.
+uint32_t lookback_for(const std::array<uint32_t, kMaxLookback + 1>& mx, uint32_t w) {
+  for (uint32_t k = 1; k <= kMaxLookback; ++k)
+    if (mx[k] <= std::min<uint32_t>(8, w)) return k;
+  uint32_t best = kMaxLookback;
+  for (uint32_t k = 1; k <= kMaxLookback; ++k)
+    if (mx[k] < mx[best]) best = k;
+  return mx[best] <= w ? best : 0u;
+}
+
 int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std::unique_ptr<Set>& out) {
   if (!hs || n_dfa == 0) return COEX_EINVAL;
   auto S = std::make_unique<Set>();
@@ -645,21 +672,16 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
     step_of[i] = (o && o->step == 1) ? 1u : (t2_ok ? 2u : 1u);
     (step_of[i] == 2 ? S->any_step2 : S->any_step1) = true;
   }
-  // lookback per automaton: the shortest whose largest candidate list fits
-  // one batch of registers (8), else the one with the fewest candidates
+  S->wmax = wmax;
   S->k_of.resize(n_dfa);
+  S->pss_max.resize(n_dfa);
+  S->sync_of.resize(n_dfa);
   uint32_t W = 1;
   for (uint32_t i = 0; i < n_dfa; ++i) {
     const Dfa& d = *ds[i];
-    uint32_t k = 0;
-    for (uint32_t kk = 1; kk <= kMaxLookback && !k; ++kk)
-      if (d.pss[kk].max_size <= std::min<uint32_t>(8, wmax)) k = kk;
-    if (!k) {
-      uint32_t best = kMaxLookback;
-      for (uint32_t kk = 1; kk <= kMaxLookback; ++kk)
-        if (d.pss[kk].max_size < d.pss[best].max_size) best = kk;
-      if (d.pss[best].max_size <= wmax) k = best;
-    }
+    for (uint32_t kk = 0; kk <= kMaxLookback; ++kk) S->pss_max[i][kk] = kk ? d.pss[kk].max_size : d.n_states;
+    S->sync_of[i] = d.sync_depth;
+    const uint32_t k = lookback_for(S->pss_max[i], wmax);
     if (!k) return COEX_EUNSUPPORTED;
     S->k_of[i] = k;
     W = std::max(W, d.pss[k].max_size);
@@ -739,11 +761,20 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
       G.off_tab[e] = G.step == 2 ? img.add(t2.data(), t2.size() * 4) : G.off_t1[e];
     }
   }
-  std::vector<size_t> off_po(n_dfa), off_ps(n_dfa);
+  // PSS tables: every lookback some width cap up to wmax selects
+  S->pss_off_at.assign(n_dfa, {});
+  S->pss_states_at.assign(n_dfa, {});
   for (uint32_t i = 0; i < n_dfa; ++i) {
-    const PssTable& P = ds[i]->pss[S->k_of[i]];
-    off_po[i] = img.add(P.off.data(), P.off.size() * 4);
-    off_ps[i] = img.add(P.states.data(), P.states.size() * 2);
+    S->pss_off_at[i].fill(SIZE_MAX);
+    S->pss_states_at[i].fill(SIZE_MAX);
+    for (uint32_t w = 1; w <= wmax; w <<= 1) {
+      for (const uint32_t k : {lookback_for(S->pss_max[i], w), S->k_of[i]}) {
+        if (!k || S->pss_off_at[i][k] != SIZE_MAX) continue;
+        const PssTable& P = ds[i]->pss[k];
+        S->pss_off_at[i][k] = img.add(P.off.data(), P.off.size() * 4);
+        S->pss_states_at[i][k] = img.add(P.states.data(), P.states.size() * 2);
+      }
+    }
   }
   int rc = S->buf.reserve(img.host.size(), S->device);
   if (rc) return rc;
@@ -756,8 +787,8 @@ int build_set(const coex_dfa* const* hs, uint32_t n_dfa, const coex_opts* o, std
       D.q0s = base[i] + (ds[i]->q0 << shift_of[i]);
       D.k = S->k_of[i];
       D.group = S->group_of[i];
-      D.pss_off = reinterpret_cast<const uint32_t*>(S->buf.p + off_po[i]);
-      D.pss_states = reinterpret_cast<const uint16_t*>(S->buf.p + off_ps[i]);
+      D.pss_off = reinterpret_cast<const uint32_t*>(S->buf.p + S->pss_off_at[i][D.k]);
+      D.pss_states = reinterpret_cast<const uint16_t*>(S->buf.p + S->pss_states_at[i][D.k]);
     }
     S->group_dev[e].resize(S->groups.size());
     for (size_t g = 0; g < S->groups.size(); ++g) {
@@ -839,11 +870,38 @@ uint64_t default_chunk(const Batch& B, uint64_t lane_bases) {
 }
 
 // Descriptors and records for the current chunk length.
+// The batch's lookbacks under its width cap (a power of two up to the
+// set's cap): descriptors, largest candidate list, convergence bounds.
+int apply_width(Batch& B) {
+  const Set& S = *B.set;
+  const uint32_t cap = B.width_cap ? B.width_cap : S.wmax;
+  B.dfa_dev = S.dfa_dev[B.scan_enc];
+  B.W = 1;
+  B.max_sync = 0;
+  B.may_nc = false;
+  for (uint32_t i = 0; i < S.n_dfa; ++i) {
+    const uint32_t k = lookback_for(S.pss_max[i], cap);
+    if (!k || S.pss_off_at[i][k] == SIZE_MAX) return COEX_EUNSUPPORTED;
+    DfaD& D = B.dfa_dev[i];
+    D.k = k;
+    D.pss_off = reinterpret_cast<const uint32_t*>(S.buf.p + S.pss_off_at[i][k]);
+    D.pss_states = reinterpret_cast<const uint16_t*>(S.buf.p + S.pss_states_at[i][k]);
+    B.W = std::max(B.W, S.pss_max[i][k]);
+    if (S.sync_of[i] == kNoSync) B.may_nc = true;
+    else B.max_sync = std::max(B.max_sync, S.sync_of[i] + k);
+  }
+  return COEX_OK;
+}
+
 int layout(Batch& B) {
   const Set& S = *B.set;
   B.convert = B.enc == 0;
   B.scan_enc = 1;
   const int e = B.scan_enc;
+  {
+    const int rcw = apply_width(B);
+    if (rcw) return rcw;
+  }
   const uint64_t C = B.chunk;
   const size_t ng = S.groups.size();
   // entries: (group, sequence) with the pair slots of that group
@@ -897,7 +955,7 @@ int layout(Batch& B) {
   B.n_slots = (uint32_t)slot_dfa.size();
   // chunks may fail to converge only when an automaton's synchronising depth
   // (plus its lookback) reaches the chunk length
-  B.needs_nc = S.may_not_converge_below || S.max_sync >= C;
+  B.needs_nc = B.may_nc || B.max_sync >= C;
   // 2-bit copies of byte sequences: codes then mask per sequence, 16-byte aligned
   std::vector<SeqD> scan_seqs = B.seqs;
   std::vector<uint64_t> prefix(B.seqs.size() + 1, 0);
@@ -922,7 +980,7 @@ int layout(Batch& B) {
   const size_t o_seq = img.add(scan_seqs.data(), scan_seqs.size() * sizeof(SeqD));
   const size_t o_src = img.add(B.seqs.data(), B.seqs.size() * sizeof(SeqD));
   const size_t o_pre = img.add(prefix.data(), prefix.size() * 8);
-  const size_t o_dfa = img.add(S.dfa_dev[e].data(), S.dfa_dev[e].size() * sizeof(DfaD));
+  const size_t o_dfa = img.add(B.dfa_dev.data(), B.dfa_dev.size() * sizeof(DfaD));
   const size_t o_ent = img.add(entries.data(), entries.size() * sizeof(EntryD));
   const size_t o_unit = img.add(units.data(), units.size() * sizeof(UnitD));
   const size_t o_grp = img.add(groups.data(), groups.size() * sizeof(GroupD));
@@ -942,9 +1000,9 @@ int layout(Batch& B) {
   if (B.needs_nc) {
     r_ts = take(NL * 4);
     r_m = take(NL * 4);
-    r_init = take(NL * S.W * 4);
-    r_ne = take(NL * S.W * 4);
-    r_nc = take(NL * S.W * 4);
+    r_init = take(NL * B.W * 4);
+    r_ne = take(NL * B.W * 4);
+    r_nc = take(NL * B.W * 4);
   }
   rc = B.recs.reserve(off, B.device);
   if (rc) return rc;
@@ -970,8 +1028,8 @@ int layout(Batch& B) {
   A.bcast_off = tab_max;
   B.lds_bytes = tab_max + 16;
   A.chunk = C;
-  A.max_cand = S.W;
-  A.nc_stride = S.W;
+  A.max_cand = B.W;
+  A.nc_stride = B.W;
   A.n_counts = B.n_pairs;
   A.task_ctr = reinterpret_cast<uint32_t*>(rp + r_ctr);
   A.fix_count = reinterpret_cast<uint32_t*>(rp + r_fc);
@@ -1054,6 +1112,11 @@ int build_batch(const Set* S, const coex_seq* seqs, uint32_t n_seq, const uint32
   int rc = device_cus(B->device, B->n_cu);
   if (rc) return rc;
   B->flags = o ? o->flags : 0u;
+  if (o && o->width) {
+    // caps the set has PSS tables for: powers of two up to its own
+    if (o->width > S->wmax || (o->width & (o->width - 1))) return COEX_EINVAL;
+    B->width_cap = o->width;
+  }
   if (o && o->chunk) {
     // per-chunk tail counters are 32-bit: the last chunk holds under two
     // chunks' bases, at most 255 pattern ends per base
@@ -1170,41 +1233,64 @@ int coex_batch_run(coex_batch* b, uint64_t* counts_dev, void* stream) {
   }
 }
 
-int coex_batch_tune(coex_batch* b, uint64_t* counts_dev, void* stream, uint64_t* chunk_out) {
+int coex_batch_tune(coex_batch* b, uint64_t* counts_dev, void* stream, uint64_t* chunk_out, uint32_t* width_out) {
   if (!b || !chunk_out) return COEX_EINVAL;
   try {
     hipStream_t st = (hipStream_t)stream;
+    const coex_dfa_set& S = *b->set;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return COEX_EDEVICE;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return COEX_EDEVICE; }
     const uint32_t keep_flags = b->flags;
     b->flags &= ~(COEX_FLAG_GRAPH | COEX_FLAG_TIME | COEX_FLAG_CHECK);
+    // width caps 1, 2, 4, ... up to the set's: each distinct choice of
+    // lookbacks once (caps that select the same lookbacks run the same work)
+    std::vector<uint32_t> caps;
+    std::vector<std::vector<uint32_t>> seen;
+    for (uint32_t w = 1; w <= S.wmax; w <<= 1) {
+      std::vector<uint32_t> ks(S.n_dfa);
+      bool ok = true;
+      for (uint32_t i = 0; i < S.n_dfa && ok; ++i) {
+        ks[i] = coex::batch::lookback_for(S.pss_max[i], w);
+        ok = ks[i] != 0;
+      }
+      if (!ok || std::find(seen.begin(), seen.end(), ks) != seen.end()) continue;
+      seen.push_back(ks);
+      caps.push_back(w);
+    }
     uint64_t best = b->chunk;
+    uint32_t best_w = b->width_cap;
     float best_ms = 1e30f;
     int rc = COEX_OK;
-    for (uint64_t c = 4096; c <= (1ull << 20) && rc == COEX_OK; c *= 4) {
-      b->chunk = c;
-      rc = coex::batch::layout(*b);
+    for (const uint32_t w : caps) {
+      for (uint64_t c = 4096; c <= (1ull << 20) && rc == COEX_OK; c *= 4) {
+        b->width_cap = w;
+        b->chunk = c;
+        rc = coex::batch::layout(*b);
+        if (rc) break;
+        rc = coex::batch::run(*b, counts_dev, st);  // warm-up
+        if (rc) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = COEX_EDEVICE; break; }
+        rc = coex::batch::run(*b, counts_dev, st);
+        if (rc) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = COEX_EDEVICE; break; }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = COEX_EDEVICE; break; }
+        if (ms < best_ms) { best_ms = ms; best = c; best_w = w; }
+      }
       if (rc) break;
-      rc = coex::batch::run(*b, counts_dev, st);  // warm-up
-      if (rc) break;
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = COEX_EDEVICE; break; }
-      rc = coex::batch::run(*b, counts_dev, st);
-      if (rc) break;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = COEX_EDEVICE; break; }
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = COEX_EDEVICE; break; }
-      if (ms < best_ms) { best_ms = ms; best = c; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->flags = keep_flags;
     b->chunk = best;
     b->fixed_chunk = best;
+    b->width_cap = best_w;
     const int rc2 = coex::batch::layout(*b);
     if (rc) return rc;
     if (rc2) return rc2;
     *chunk_out = best;
+    if (width_out) *width_out = best_w ? best_w : S.wmax;
     return COEX_OK;
   } catch (...) {
     return COEX_EINTERNAL;
@@ -1215,7 +1301,7 @@ int coex_batch_info(const coex_batch* b, coex_batch_info_t* info) {
   if (!b || !info) return COEX_EINVAL;
   const coex_dfa_set& S = *b->set;
   info->chunk = b->chunk;
-  info->width = S.W;
+  info->width = b->W;
   info->step = S.any_step2 ? (S.any_step1 ? 3u : 2u) : 1u;
   info->n_groups = (uint32_t)S.groups.size();
   info->n_pairs = b->n_pairs;

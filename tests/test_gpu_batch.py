@@ -181,11 +181,23 @@ def test_tuner_and_convenience(coex):
     exp = _expect(pats, host)
     dset = coex.DfaSet([p.dfa for p in pats])
     b = coex.Batch(dset, dev, check=True)
-    c = b.tune()
-    say("tuned chunk", c)
+    c, w = b.tune()
+    say("tuned chunk", c, "width cap", w)
     assert 4096 <= c <= (1 << 20)
+    assert w in (1, 2, 4, 8, 16, 32, 64)
     assert b.info().chunk == c
     assert b.run().cpu().numpy().view(np.uint64).tolist() == exp.tolist()
+    # every width cap the set allows gives the same counts
+    for cap in (1, 2, 4, 8, 16, 32, 64):
+        try:
+            bw = coex.Batch(dset, dev, check=True, width=cap, chunk=4096)
+        except coex.CoexError as e:  # some automaton needs more candidates than the cap
+            assert e.name == "EUNSUPPORTED", e
+            continue
+        say("width cap", cap, bw.info())
+        assert bw.info().width <= cap
+        assert bw.run().cpu().numpy().view(np.uint64).tolist() == exp.tolist()
+        bw.free()
     got = coex.count_batched([p.dfa for p in pats], dev).cpu().numpy().view(np.uint64)
     assert got.tolist() == exp.tolist()
 
@@ -224,9 +236,9 @@ def test_batched_config_all_pairs(coex):
     seqs = [coex.DeviceSeq(dbuf[o:o + max(n, 1)], n, coex.ENC_BYTE) for o, n in zip(offs, lengths)]
     dset = coex.DfaSet([p.dfa for p in pats])
     tb = coex.Batch(dset, seqs)
-    chunk = tb.tune()
+    chunk, width = tb.tune()
     tb.free()
-    b = coex.Batch(dset, seqs, chunk=chunk, graph=True, check=False)
+    b = coex.Batch(dset, seqs, chunk=chunk, width=width, graph=True, check=False)
     got = b.run().cpu().numpy().view(np.uint64).reshape(len(lengths), len(pats))
     got2 = b.run().cpu().numpy().view(np.uint64).reshape(len(lengths), len(pats))
     say("batched: gpu done", b.info())
