@@ -151,7 +151,8 @@ def cpu_baseline(name: str, w, gpu_counts):
     if name == "genome":
         packed, mask = w["host"]
         seq = oracle.twobit_seq(packed, mask, w["n"])
-        counts = oracle.count_kmers(w["patterns"], seq)[0]
+        counts, pos, pat = oracle.count_kmers(w["patterns"], seq, positions=True)
+        w["oracle_positions"] = (pos, pat)
     elif name == "parity":
         packed, mask = w["host"]
         counts = oracle.scan_table(oracle.make_table(*w["table"], 1), oracle.twobit_seq(packed, mask, w["n"]))[0]
@@ -523,6 +524,20 @@ def main():
     # after the timed region)
     device_failures = coex.errors()
     gpu_counts = out[: info.n_patterns].cpu().numpy().view(np.uint64)
+    positions = None
+    if args.workload == "genome":
+        # per-pattern end positions of the whole sequence (coex_find: one pass,
+        # one host sync, then a sort of the appended keys), timed on its own
+        coex.find(dfa, seq)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            pos, pat = coex.find(dfa, seq)
+        torch.cuda.synchronize()
+        find_ms = (time.perf_counter() - t1) / 5 * 1e3
+        positions = {"ms": round(find_ms, 3), "matches": int(pos.numel()),
+                     "gbases_per_s": round(w["n"] / (find_ms * 1e-3) / 1e9, 1)}
+        log("find: %.3f ms, %d matches" % (find_ms, pos.numel()))
     value = w["n"] / (ms_step * 1e-3) / 1e9
     log("wall %.3f s for %d steps; events %.3f ms/step; scan kernel %.3f ms avg over %d launches"
         % (wall, args.steps, ms_step, k_avg_ms, k_n))
@@ -552,6 +567,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "device_check_failures": device_failures,
+        "positions": positions,
         "config": {"workload": w["desc"], "bases": w["n"], "automaton_states": info.n_states,
                    "patterns": info.n_patterns, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_tail", "achieved": round(achieved, 1),
@@ -565,6 +581,10 @@ def main():
         cb, exact = cpu_baseline(args.workload, w, gpu_counts)
         res["cpu_baseline"] = cb
         res["exact"] = exact
+        if positions is not None and "oracle_positions" in w:
+            epos, epat = w["oracle_positions"]
+            positions["exact"] = bool(pos.cpu().numpy().tolist() == epos.tolist() and
+                                      pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist())
         log("oracle: %s; exact=%s" % (cb["sample"], exact))
         if args.workload == "genome":
             usable = host_cpu()["usable_cpus"]

@@ -232,6 +232,39 @@ int coex_count_chunks(const coex_dfa* dfa, const coex_seq* seq, uint32_t chunk, 
    (flags_out NULL), EDEVICE. */
 int coex_errors_async(void* stream, uint32_t* flags_out);
 
+/* ------------------------------------------------------------ FASTA ingest
+   Host-side parsing of FASTA text (not part of the paper's method: the input
+   format of the sequences it scans).  Lines starting with '>' are headers and
+   start records; all other lines hold bases; line breaks ("\n", "\r\n") and
+   blanks are dropped; bases before the first header form a record of their
+   own (a text without headers is one record).  The records are written back
+   to back, so the whole output can be scanned at once, or record r alone as
+   the n = rec_len[r] bases from first_base = rec_start[r].  Work is split over
+   `threads` host threads (0 = every hardware thread) at line starts. */
+#define COEX_FASTA_SOFTMASK 1u /* lowercase letters (soft-masked bases) read as N, a reset */
+#define COEX_FASTA_SEPARATE 2u /* one N between consecutive records: a whole-output scan never
+                                  matches across records */
+
+/* Sizes the output: *n_records, and *n_bases (separators included). */
+int coex_fasta_measure(const char* text, uint64_t len, uint32_t flags, uint32_t threads, uint64_t* n_records,
+                       uint64_t* n_bases);
+
+/* Parses into host buffers.  COEX_ENC_BYTE: `bases` receives one byte per
+   base as written in the text (with COEX_FASTA_SOFTMASK, lowercase letters
+   as 'N'; separators are 'N'); n_mask is unused.  COEX_ENC_2BIT: `bases`
+   receives ceil(n/4) bytes of codes (A=0 C=1 G=2 T=3, four per byte from the
+   low bits) and n_mask, if not NULL, ceil(n/8) bytes whose bit i is set for
+   every base i that is not A/C/G/T in either case (and for soft-masked bases
+   and separators).  rec_start[r] / rec_len[r]: first base and length of
+   record r in the output; rec_header[r]: text offset of its '>' (UINT64_MAX
+   for a record before the first header); each may be NULL.  *n_records and
+   *n_bases are always set; ECAPACITY (nothing written) when n_bases exceeds
+   cap_bases or, with a record array given, n_records exceeds cap_records.
+   Errors: EINVAL, ECAPACITY, ENOMEM. */
+int coex_fasta_read(const char* text, uint64_t len, int32_t encoding, uint32_t flags, uint32_t threads,
+                    void* bases, uint8_t* n_mask, uint64_t cap_bases, uint64_t* rec_start, uint64_t* rec_len,
+                    uint64_t* rec_header, uint64_t cap_records, uint64_t* n_records, uint64_t* n_bases);
+
 /* The paper's own method on the host's cores (Section III, Algorithm 1), a
    CPU baseline reported beside the GPU scan (never used by the calls above):
    `n_chunks` equal chunks (0 = one per thread; the last takes the remainder)
@@ -341,8 +374,10 @@ int coex_count_batched(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_s
    into a device arena of `hbm_budget` bytes, copied on a copy stream while
    earlier batches run (in pieces of `copy_piece` bytes, the request with the
    fewest bytes left first), and every admitted request whose copy has
-   finished is launched in the next batch (continuous batching; up to two batches queued
-   on the compute stream).  A request's count is its pair's count in a batch,
+   finished is launched in the next batch (continuous batching; up to two
+   batches in flight, each on a compute stream of its own, so one can run
+   while the other is being launched or drained).  A request's count is its
+   pair's count in a batch,
    so it is the same alone or in any mix.  One worker thread per server;
    submit and wait may be called from any thread. */
 

@@ -29,7 +29,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -
 
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_count_noalloc", "coex_find",
-            "coex_count_chunks", "coex_count_host", "coex_errors_async",
+            "coex_count_chunks", "coex_count_host", "coex_errors_async", "coex_fasta_measure", "coex_fasta_read",
             "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
             "coex_batch_update", "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free",
             "coex_server_create", "coex_server_submit", "coex_server_wait", "coex_server_stats", "coex_server_free",
@@ -111,6 +111,8 @@ def _lib():
         L.coex_count.argtypes = [p, p, p, p, p]
         L.coex_count_noalloc.argtypes = [p, p, p, p, p]
         L.coex_errors_async.argtypes = [p, p]
+        L.coex_fasta_measure.argtypes = [p, u64, u32, u32, p, p]
+        L.coex_fasta_read.argtypes = [p, u64, ctypes.c_int32, u32, u32, p, p, u64, p, p, p, u64, p, p]
         L.coex_count_host.argtypes = [p, p, p, u64, ctypes.c_int32, u32, u64, u64, p]
         L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
         L.coex_count_chunks.argtypes = [p, p, u32, p, p, p, p]
@@ -262,6 +264,58 @@ def _pad16(arr: np.ndarray) -> np.ndarray:
     padded = np.zeros(((n + 127) // 128) * 128 or 128, dtype=np.uint8)
     padded[:n] = arr
     return padded
+
+
+# ------------------------------------------------------------------ FASTA
+FASTA_SOFTMASK = 1
+FASTA_SEPARATE = 2
+
+
+@dataclass
+class FastaRecord:
+    name: str     # header line without '>' ("" for bases before the first header)
+    start: int    # first base in the parsed output
+    length: int
+
+
+def read_fasta(text: bytes, encoding: int = ENC_2BIT, softmask: bool = False, separate: bool = False,
+               threads: int = 0):
+    """Parses FASTA text on the host (coex_fasta_read): returns (bases, mask,
+    n, records); bases are bytes or packed 2-bit codes with `mask` the N bits
+    (None for bytes)."""
+    text = bytes(text)
+    flags = (FASTA_SOFTMASK if softmask else 0) | (FASTA_SEPARATE if separate else 0)
+    nr, nb = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(_lib().coex_fasta_measure(text, len(text), flags, threads, ctypes.byref(nr), ctypes.byref(nb)),
+           "fasta_measure")
+    n, R = int(nb.value), int(nr.value)
+    if encoding == ENC_BYTE:
+        data, mask = np.zeros(max(1, n), np.uint8), None
+    else:
+        data, mask = np.zeros(max(1, (n + 3) // 4), np.uint8), np.zeros(max(1, (n + 7) // 8), np.uint8)
+    start, length, head = (np.zeros(max(1, R), np.uint64) for _ in range(3))
+    _check(_lib().coex_fasta_read(text, len(text), encoding, flags, threads, data.ctypes.data,
+                                  None if mask is None else mask.ctypes.data, n, start.ctypes.data,
+                                  length.ctypes.data, head.ctypes.data, R, ctypes.byref(nr), ctypes.byref(nb)),
+           "fasta_read")
+    recs = []
+    for r in range(R):
+        h = int(head[r])
+        if h == (1 << 64) - 1:
+            name = ""
+        else:
+            e = text.find(b"\n", h)
+            name = text[h + 1: e if e >= 0 else len(text)].decode("latin-1").strip()
+        recs.append(FastaRecord(name, int(start[r]), int(length[r])))
+    return data, mask, n, recs
+
+
+def fasta_to_device(text: bytes, encoding: int = ENC_2BIT, softmask: bool = False, separate: bool = False,
+                    threads: int = 0, device: str = "cuda"):
+    """read_fasta, then the bases to the device: (DeviceSeq of the whole
+    output, records); record r alone is seq.sub(rec.start, rec.length)."""
+    data, mask, n, recs = read_fasta(text, encoding, softmask, separate, threads)
+    return to_device(data, n=n, encoding=encoding, nmask=mask, device=device), recs
 
 
 def to_device(data: np.ndarray, n: Optional[int] = None, encoding: int = ENC_BYTE,

@@ -46,6 +46,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     obj_host = os.path.join(CSRC, "compile%s.o" % sfx)
     obj_serve = os.path.join(CSRC, "serve%s.o" % sfx)
     obj_hm = os.path.join(CSRC, "host_method%s.o" % sfx)
+    obj_fa = os.path.join(CSRC, "fasta%s.o" % sfx)
     dev_srcs = ["coex.hip", "batch.hip", "sort.hip"] + ["tail_%s_%s.hip" % (e, k) for e in ("byte", "2bit")
                                             for k in ("count", "hist", "pos")]
     obj_dev = [os.path.join(CSRC, "%s%s.o" % (os.path.splitext(f)[0], sfx)) for f in dev_srcs]
@@ -60,6 +61,9 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True),
                 subprocess.Popen(["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-c", "-o", obj_hm] + inc +
                                  [os.path.join(CSRC, "host_method.cpp")],
+                                 stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True),
+                subprocess.Popen(["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-c", "-o", obj_fa] + inc +
+                                 [os.path.join(CSRC, "fasta.cpp")],
                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)]
         for src, obj in zip(dev_srcs, obj_dev):
             cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + inc + ["-c", "-o", obj, os.path.join(CSRC, src)]

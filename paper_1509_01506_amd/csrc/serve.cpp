@@ -97,7 +97,8 @@ struct Req {
   bool done = false;
 };
 
-struct Slot {  // one batch in flight
+struct Slot {  // one batch in flight, on a compute stream of its own (two batches can overlap)
+  hipStream_t st = nullptr;
   coex_batch* batch = nullptr;
   uint64_t* counts_dev = nullptr;
   uint64_t* counts_host = nullptr;  // pinned
@@ -115,7 +116,7 @@ struct coex_server {
   int device = 0;
   coex_dfa_set* set = nullptr;
   uint32_t n_dfa = 0;
-  hipStream_t copy_st = nullptr, comp_st = nullptr;
+  hipStream_t copy_st = nullptr;
   char* arena_buf = nullptr;
   Arena arena;
   uint32_t max_batch = 1024;
@@ -306,12 +307,12 @@ bool launch(coex_server* S) {
   }
   int st = grow_slot(*sl, n);
   if (st == COEX_OK) st = coex_batch_update(sl->batch, seqs.data(), n, ps.data(), pd.data(), n);
-  if (st == COEX_OK && hipEventRecord(sl->start, S->comp_st) != hipSuccess) st = COEX_EDEVICE;
-  if (st == COEX_OK) st = coex_batch_run(sl->batch, sl->counts_dev, S->comp_st);
+  if (st == COEX_OK && hipEventRecord(sl->start, sl->st) != hipSuccess) st = COEX_EDEVICE;
+  if (st == COEX_OK) st = coex_batch_run(sl->batch, sl->counts_dev, sl->st);
   if (st == COEX_OK &&
-      hipMemcpyAsync(sl->counts_host, sl->counts_dev, (size_t)n * 8, hipMemcpyDeviceToHost, S->comp_st) != hipSuccess)
+      hipMemcpyAsync(sl->counts_host, sl->counts_dev, (size_t)n * 8, hipMemcpyDeviceToHost, sl->st) != hipSuccess)
     st = COEX_EDEVICE;
-  if (st == COEX_OK && hipEventRecord(sl->done, S->comp_st) != hipSuccess) st = COEX_EDEVICE;
+  if (st == COEX_OK && hipEventRecord(sl->done, sl->st) != hipSuccess) st = COEX_EDEVICE;
   S->resident.swap(wait);
   const auto now = Clock::now();
   if (st != COEX_OK) {
@@ -372,10 +373,10 @@ coex_server::~coex_server() {
     if (sl.counts_host) (void)hipHostFree(sl.counts_host);
     if (sl.start) (void)hipEventDestroy(sl.start);
     if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
   }
   if (arena_buf) (void)hipFree(arena_buf);
   if (copy_st) (void)hipStreamDestroy(copy_st);
-  if (comp_st) (void)hipStreamDestroy(comp_st);
   if (set) coex_dfa_set_free(set);
 }
 
@@ -397,12 +398,12 @@ int coex_server_create(const coex_dfa* const* dfas, uint32_t n_dfa, const coex_s
     if (o && o->copy_piece) S->piece = o->copy_piece;
     S->inflight_cap = 3 * S->piece;
     if (hipStreamCreateWithFlags(&S->copy_st, hipStreamNonBlocking) != hipSuccess) return COEX_EDEVICE;
-    if (hipStreamCreateWithFlags(&S->comp_st, hipStreamNonBlocking) != hipSuccess) return COEX_EDEVICE;
     if (hipMalloc(&S->arena_buf, budget) != hipSuccess) return COEX_ENOMEM;
     S->arena.init(S->arena_buf, budget);
     coex_opts bo{};
     if (o) bo.chunk = o->chunk;
     for (Slot& sl : S->slots) {
+      if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess) return COEX_EDEVICE;
       rc = coex_batch_create(S->set, nullptr, 0, nullptr, nullptr, 0, &bo, &sl.batch);
       if (rc) return rc;
       if (hipEventCreate(&sl.start) != hipSuccess || hipEventCreate(&sl.done) != hipSuccess) return COEX_EDEVICE;

@@ -295,6 +295,56 @@ def test_errors_async(coex):
     assert coex.errors() == 0
 
 
+def test_fasta_records(coex):
+    # FASTA text (headers, line breaks of both kinds, soft-masked runs, an
+    # empty record) parsed on the host and scanned on the device: each record
+    # alone (first_base) and the whole output with one N between records,
+    # byte and 2-bit, soft-masking on and off; the oracle runs on the records'
+    # own bases as generated here
+    import random
+    rnd = random.Random(5)
+    kmers = synth.random_kmers(33, 5, 6) + ["ACGTA"]
+    d = coex.Dfa.kmers(kmers)
+    bodies = []
+    for r, n in enumerate([120_000, 0, 7, 250_003, 64, 90_000]):
+        b = bytearray(synth.markov_bytes(300 + r, n, with_n=True).tobytes()) if n else bytearray()
+        for _ in range(5):
+            if n > 100:
+                a = rnd.randrange(n - 50)
+                b[a:a + 40] = b[a:a + 40].lower()
+        bodies.append(bytes(b))
+    parts = []
+    for r, b in enumerate(bodies):
+        eol = b"\r\n" if r % 2 else b"\n"
+        parts.append(b">chr%d test record%s" % (r, eol))
+        w = 60 + 20 * (r % 3)
+        parts += [b[i:i + w] + eol for i in range(0, len(b), w)]
+    text = b"".join(parts)
+    for soft in (False, True):
+        recs_bytes = [bytes(ord("N") if soft and 97 <= c <= 122 else c for c in b) for b in bodies]
+        joined = b"N".join(recs_bytes)
+        ec_all, epos, epat = oracle.count_kmers(kmers, oracle.byte_seq(np.frombuffer(joined, np.uint8)),
+                                                positions=True)
+        for enc in (coex.ENC_BYTE, coex.ENC_2BIT):
+            seq, recs = coex.fasta_to_device(text, encoding=enc, softmask=soft, separate=True)
+            assert [r.name for r in recs] == ["chr%d test record" % i for i in range(len(bodies))]
+            assert seq.n == len(joined)
+            total = np.zeros(len(kmers), np.uint64)
+            for r, rb in enumerate(recs_bytes):
+                say("fasta", soft, enc, r)
+                assert recs[r].length == len(rb)
+                ec = oracle.count_kmers(kmers, oracle.byte_seq(np.frombuffer(rb, np.uint8)))[0] if rb else \
+                    np.zeros(len(kmers), np.uint64)
+                if rb:
+                    assert gpu_counts(coex, d, seq.sub(recs[r].start, recs[r].length)).tolist() == ec.tolist()
+                total += ec
+            assert total.tolist() == ec_all.tolist()  # the separators stop cross-record matches
+            assert gpu_counts(coex, d, seq).tolist() == ec_all.tolist()
+            pos, pat = coex.find(d, seq)
+            assert pos.cpu().numpy().tolist() == epos.tolist()
+            assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
+
+
 def test_count_chunks_records(coex):
     n = 50_000
     seq = synth.markov_bytes(25, n, with_n=True)
@@ -386,10 +436,14 @@ def test_full_genome(coex):
     got2 = gpu_counts(coex, d, s, step=2)
     got32 = gpu_counts(coex, d, s, step=3, chains=2)
     got22 = gpu_counts(coex, d, s, step=2, chains=2)
-    say("genome full: gpu done", int(got.sum()))
-    expect = oracle.count_kmers(kmers, oracle.twobit_seq(packed, mask, n))[0]
+    pos, pat = coex.find(d, s)
+    say("genome full: gpu done", int(got.sum()), "matches", pos.numel())
+    expect, epos, epat = oracle.count_kmers(kmers, oracle.twobit_seq(packed, mask, n), positions=True)
     say("genome full: oracle done", int(expect.sum()))
     assert got.tolist() == expect.tolist()
+    # per-pattern end positions of the whole sequence ("count and extract")
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+    assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
     assert got3.tolist() == expect.tolist()
     assert got2.tolist() == expect.tolist()
     assert got32.tolist() == expect.tolist()
