@@ -232,6 +232,40 @@ int coex_count_chunks(const coex_dfa* dfa, const coex_seq* seq, uint32_t chunk, 
    (flags_out NULL), EDEVICE. */
 int coex_errors_async(void* stream, uint32_t* flags_out);
 
+/* ------------------------------------------------------------ pattern partitioning
+   Pattern-based partitioning (Section III.A, Fig. 1b): the patterns split
+   into parts, one automaton each, every part scanning the same sequence.  It
+   takes k-mer sets whose single automaton would be too large for the device
+   tables (more than 4096 states) or for the three-symbol tables (more than
+   1023), and gives short inputs more work to run at once. */
+typedef struct coex_partition coex_partition;
+
+/* Splits `n` k-mers (as for coex_compile_kmers; pattern id = index) into
+   parts whose Aho-Corasick automata have at most `max_states` states (0 =
+   1023): patterns in sorted order, a part closed when the next pattern's new
+   prefixes would take its trie past the budget.  Errors: EINVAL, EALPHABET,
+   ETOOBIG (one k-mer alone needs more states than the budget), ENOMEM. */
+int coex_partition_kmers(const char* const* kmers, uint32_t n, uint32_t max_states, coex_partition** out);
+
+int coex_partition_info(const coex_partition* p, uint32_t* n_parts, uint32_t* n_patterns);
+
+/* Part i: its automaton (owned by the partition) and the global ids of its
+   patterns (ids[j] = global id of the part's pattern j). */
+int coex_partition_part(const coex_partition* p, uint32_t i, const coex_dfa** dfa, const uint32_t** ids,
+                        uint32_t* n);
+
+/* Per-pattern counts of every part over `seq` into counts_dev
+   uint64[n_patterns] (global ids).  The parts run as coex_count on up to four
+   streams of the partition's own, after the work already queued on `stream`;
+   the counts are complete, and the parts' consistency failures handed to
+   `stream`'s kept word (coex_errors_async), once `stream` passes the call's
+   last kernel.  Calls on one partition must not overlap.  Errors: as for
+   coex_count. */
+int coex_count_partitioned(coex_partition* p, const coex_seq* seq, uint64_t* counts_dev, const coex_opts* opts,
+                           void* stream);
+
+void coex_partition_free(coex_partition* p);
+
 /* ------------------------------------------------------------ FASTA ingest
    Host-side parsing of FASTA text (not part of the paper's method: the input
    format of the sequences it scans).  Lines starting with '>' are headers and

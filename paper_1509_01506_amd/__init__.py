@@ -30,6 +30,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_count_noalloc", "coex_find",
             "coex_count_chunks", "coex_count_host", "coex_errors_async", "coex_fasta_measure", "coex_fasta_read",
+            "coex_partition_kmers", "coex_partition_info", "coex_partition_part", "coex_count_partitioned",
+            "coex_partition_free",
             "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
             "coex_batch_update", "coex_batch_run", "coex_batch_tune", "coex_batch_info", "coex_batch_free",
             "coex_server_create", "coex_server_submit", "coex_server_wait", "coex_server_stats", "coex_server_free",
@@ -67,7 +69,7 @@ class _BatchInfo(ctypes.Structure):
 
 
 _L = None
-_VOID = ("coex_dfa_free", "coex_strerror", "coex_version", "coex_dfa_set_free", "coex_batch_free",
+_VOID = ("coex_dfa_free", "coex_partition_free", "coex_strerror", "coex_version", "coex_dfa_set_free", "coex_batch_free",
          "coex_server_free")
 
 
@@ -112,6 +114,12 @@ def _lib():
         L.coex_count_noalloc.argtypes = [p, p, p, p, p]
         L.coex_errors_async.argtypes = [p, p]
         L.coex_fasta_measure.argtypes = [p, u64, u32, u32, p, p]
+        L.coex_partition_kmers.argtypes = [p, u32, u32, p]
+        L.coex_partition_info.argtypes = [p, p, p]
+        L.coex_partition_part.argtypes = [p, u32, p, p, p]
+        L.coex_count_partitioned.argtypes = [p, p, p, p, p]
+        L.coex_partition_free.argtypes = [p]
+        L.coex_partition_free.restype = None
         L.coex_fasta_read.argtypes = [p, u64, ctypes.c_int32, u32, u32, p, p, u64, p, p, p, u64, p, p]
         L.coex_count_host.argtypes = [p, p, p, u64, ctypes.c_int32, u32, u64, u64, p]
         L.coex_find.argtypes = [p, p, p, p, u64, p, p, p]
@@ -264,6 +272,54 @@ def _pad16(arr: np.ndarray) -> np.ndarray:
     padded = np.zeros(((n + 127) // 128) * 128 or 128, dtype=np.uint8)
     padded[:n] = arr
     return padded
+
+
+# ------------------------------------------------------------------ pattern partitioning
+class Partition:
+    """Pattern-based partitioning of a k-mer set (coex_partition_kmers): parts
+    of at most `max_states` states each (0 = 1023), every part scanning the
+    same sequence; counts per global pattern id."""
+
+    def __init__(self, kmers: Sequence[str], max_states: int = 0):
+        enc = [k.encode("ascii") for k in kmers]
+        arr = (ctypes.c_char_p * len(enc))(*enc)
+        out = ctypes.c_void_p()
+        _check(_lib().coex_partition_kmers(ctypes.cast(arr, ctypes.c_void_p), len(enc), max_states,
+                                           ctypes.byref(out)), "partition_kmers")
+        self._h = out
+        n_parts, n_pat = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        _check(_lib().coex_partition_info(self._h, ctypes.byref(n_parts), ctypes.byref(n_pat)), "partition_info")
+        self.n_parts, self.n_patterns = int(n_parts.value), int(n_pat.value)
+
+    def part(self, i: int):
+        """(n_states of part i's automaton, global ids of its patterns)."""
+        d, ids, n = ctypes.c_void_p(), ctypes.POINTER(ctypes.c_uint32)(), ctypes.c_uint32(0)
+        _check(_lib().coex_partition_part(self._h, i, ctypes.byref(d), ctypes.byref(ids), ctypes.byref(n)),
+               "partition_part")
+        info = _Info()
+        _check(_lib().coex_dfa_info(d, ctypes.byref(info)), "dfa_info")
+        return int(info.n_states), [int(ids[j]) for j in range(n.value)]
+
+    def count(self, seq: "DeviceSeq", out=None, check: bool = False, stream=None, **kw):
+        import torch
+        if out is None:
+            out = torch.empty(max(1, self.n_patterns), dtype=torch.int64, device=seq.bases.device)
+        s = seq._c()
+        o = _opts(check=check, **kw)
+        _check(_lib().coex_count_partitioned(self._h, ctypes.byref(s), out.data_ptr(), ctypes.byref(o),
+                                             _stream(stream)), "count_partitioned")
+        return out[: self.n_patterns]
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib().coex_partition_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ FASTA

@@ -47,7 +47,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     obj_serve = os.path.join(CSRC, "serve%s.o" % sfx)
     obj_hm = os.path.join(CSRC, "host_method%s.o" % sfx)
     obj_fa = os.path.join(CSRC, "fasta%s.o" % sfx)
-    dev_srcs = ["coex.hip", "batch.hip", "sort.hip"] + ["tail_%s_%s.hip" % (e, k) for e in ("byte", "2bit")
+    dev_srcs = ["coex.hip", "batch.hip", "sort.hip", "partition.hip"] + ["tail_%s_%s.hip" % (e, k) for e in ("byte", "2bit")
                                             for k in ("count", "hist", "pos")]
     obj_dev = [os.path.join(CSRC, "%s%s.o" % (os.path.splitext(f)[0], sfx)) for f in dev_srcs]
     tmp = out + tag

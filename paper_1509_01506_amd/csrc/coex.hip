@@ -696,6 +696,22 @@ int workspace(int dev, void* stream, size_t bytes, char*& out, Workspace*& wsp) 
   return COEX_OK;
 }
 
+}  // namespace
+
+// The kept failure word of the calls on (device, stream), creating the
+// stream's workspace if it has none yet (for calls made on other streams on
+// the caller's behalf).
+int stream_sticky(int dev, void* stream, uint32_t** out) {
+  char* buf = nullptr;
+  Workspace* w = nullptr;
+  const int rc = workspace(dev, stream, 0, buf, w);
+  if (rc) return rc;
+  *out = w->sticky;
+  return COEX_OK;
+}
+
+namespace {
+
 struct Plan {
   uint32_t shift, step, chains, block, k, group, max_cand, blocks, lds_bytes;
   uint32_t join_r;       // map row bytes of the parallel join (0: the serial join, more than kJoinFan candidates)

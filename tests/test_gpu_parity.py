@@ -345,6 +345,34 @@ def test_fasta_records(coex):
             assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
 
 
+def test_partitioned_kmer_set(coex):
+    # 1,000 12-mers, past the device tables as one automaton, split into parts
+    # of at most 1,023 (three-symbol tables) or 300 states; per-pattern counts
+    # against the oracle's own automaton of the whole set, on a long and a
+    # short input, byte and 2-bit; unchecked calls leave no kept failure
+    kmers = synth.random_kmers(61, 1000, 12)
+    n = 1_000_003
+    seq = synth.markov_bytes(62, n, with_n=True)
+    for i in range(300):  # planted occurrences
+        at = 1000 + i * 3301
+        seq[at:at + 12] = np.frombuffer(kmers[(7 * i) % 1000].encode(), dtype=np.uint8)
+    ec = oracle.count_kmers(kmers, oracle.byte_seq(seq))[0]
+    short = seq[:5000].copy()
+    es = oracle.count_kmers(kmers, oracle.byte_seq(short))[0]
+    s, s2 = dev_bytes(coex, seq), dev_2bit(coex, seq)[0]
+    ss = dev_bytes(coex, short)
+    for budget in (0, 300):
+        p = coex.Partition(kmers, max_states=budget)
+        say("partitioned", budget, p.n_parts)
+        got = lambda x, **kw: p.count(x, **kw).cpu().numpy().view(np.uint64).tolist()
+        assert got(s, check=True) == ec.tolist()
+        assert got(s2) == ec.tolist()
+        assert got(ss) == es.tolist()
+        assert got(s2.sub(1000, 5000)) == oracle.count_kmers(kmers, oracle.byte_seq(seq[1000:6000]))[0].tolist()
+        p.free()
+    assert coex.errors() == 0
+
+
 def test_count_chunks_records(coex):
     n = 50_000
     seq = synth.markov_bytes(25, n, with_n=True)
