@@ -14,11 +14,12 @@ for the dominant kernel (the speculation + chunk scan kernel, timed with HIP
 events on its stream inside the timed region), and a CPU baseline (the oracle,
 single thread, over the same sequence, which doubles as the exactness check).
 
-  python bench.py [--steps K] [--warmup W] [--workload genome|mid|small|batched|serving|parity]
+  python bench.py [--steps K] [--warmup W] [--workload genome|mid|small|batched|serving|parity|partitioned]
 """
 from __future__ import annotations
 
 import argparse
+import types
 import hashlib
 import json
 import os
@@ -100,6 +101,18 @@ def build_workload(name: str):
             bytes_per_base=0.375, find=False,
             desc="genome: 3.2e9 Markov bases (GC 0.41, 1% N runs), 2-bit packed + 1-bit N mask; "
                  "64 random 12-mers as one Aho-Corasick automaton; per-pattern counts")
+    if name == "partitioned":
+        import synth
+        packed, mask, _ = configs.genome()
+        n = configs.GENOME_N
+        kmers = synth.random_kmers(61, 1000, 12)
+        part = coex.Partition(kmers)
+        return dict(
+            n=n, enc=coex.ENC_2BIT, host=(packed, mask), dfa=None, partition=part, patterns=kmers, chunk=0,
+            bytes_per_base=0.375, find=False,
+            desc="partitioned: the genome workload's 3.2e9 bases; 1,000 random 12-mers (one automaton would pass "
+                 "the 4,096-state device tables) split into %d parts of at most 1,023 states, every part "
+                 "scanning the whole sequence; per-pattern counts" % part.n_parts)
     if name == "parity":
         packed, mask, _ = configs.genome()
         n = configs.GENOME_N
@@ -153,6 +166,9 @@ def cpu_baseline(name: str, w, gpu_counts):
         seq = oracle.twobit_seq(packed, mask, w["n"])
         counts, pos, pat = oracle.count_kmers(w["patterns"], seq, positions=True)
         w["oracle_positions"] = (pos, pat)
+    elif name == "partitioned":
+        packed, mask = w["host"]
+        counts = oracle.count_kmers(w["patterns"], oracle.twobit_seq(packed, mask, w["n"]))[0]
     elif name == "parity":
         packed, mask = w["host"]
         counts = oracle.scan_table(oracle.make_table(*w["table"], 1), oracle.twobit_seq(packed, mask, w["n"]))[0]
@@ -437,7 +453,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small", "batched", "serving", "parity"])
+    ap.add_argument("--workload", default="genome", choices=["genome", "mid", "small", "batched", "serving", "parity", "partitioned"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--clock-warmup-s", type=float, default=0.5,
                     help="untimed steps for this many seconds before the warm-up steps (sustained clocks)")
@@ -481,7 +497,12 @@ def main():
     data, mask = w["host"]
     seq = coex.to_device(data, n=w["n"], encoding=w["enc"], nmask=mask)
     dfa = w["dfa"]
-    info = dfa.info()
+    part = w.get("partition")
+    if part is not None:
+        sizes = [part.part(i)[0] for i in range(part.n_parts)]
+        info = types.SimpleNamespace(n_states=sum(sizes), n_patterns=part.n_patterns)
+    else:
+        info = dfa.info()
     torch.cuda.synchronize()
     log("resident in HBM; automaton %d states" % info.n_states)
 
@@ -490,6 +511,9 @@ def main():
     chunk = args.chunk or w["chunk"]
 
     def step(timed: bool):
+        if part is not None:
+            part.count(seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains)
+            return
         coex.count(dfa, seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains)
         if w["find"]:
             coex.find(dfa, seq, chunk=chunk, step=args.step, chains=args.chains)
@@ -543,10 +567,16 @@ def main():
         % (wall, args.steps, ms_step, k_avg_ms, k_n))
 
     algo_bytes = w["n"] * w["bytes_per_base"]
+    kernel_name = "k_tail"
+    if part is not None:
+        # the parts run on the partition's own streams (no per-launch events
+        # there): every part reads the whole sequence once per step
+        k_avg_ms = ms_step / part.n_parts
+        kernel_name = "k_tail (all parts: step time / parts)"
     achieved = algo_bytes / (k_avg_ms * 1e-3) / 1e9
     # symbols per lookup of the chunk scan (the planner's default: three for
     # an automaton of at most 1023 states, else two, else one)
-    sym = args.step or (1 if info.n_states > 1024 else (3 if info.n_states <= 1023 else 2))
+    sym = args.step or (3 if part is not None else (1 if info.n_states > 1024 else (3 if info.n_states <= 1023 else 2)))
     # lookups per base: three symbols per lookup walk 512-base blocks as ten
     # 48-base units (16 lookups) and two words (5 three- + 1 one-symbol lookup)
     per_base = {1: 1.0, 2: 0.5, 3: 172.0 / 512.0}[sym]
@@ -569,8 +599,9 @@ def main():
         "device_check_failures": device_failures,
         "positions": positions,
         "config": {"workload": w["desc"], "bases": w["n"], "automaton_states": info.n_states,
+                   **({"parts": part.n_parts} if part is not None else {}),
                    "patterns": info.n_patterns, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_tail", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(k_avg_ms, 4),
                      "algorithmic_bytes_per_launch": int(algo_bytes),

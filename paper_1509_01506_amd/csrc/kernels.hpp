@@ -522,14 +522,37 @@ struct Block<ENC_2BIT> {
     for (int i = 0; i < MW; ++i) x |= m[i];
     return x;
   }
-  // whole block inside the sequence
-  __device__ __forceinline__ void load(const ScanArgs& a, uint64_t base) {
+  __device__ __forceinline__ void load_codes(const ScanArgs& a, uint64_t base) {
     const uint4* src = reinterpret_cast<const uint4*>(a.bases + (base >> 2));
 #pragma unroll
     for (int i = 0; i < WORDS / 4; ++i) {
       uint4 t = src[i];
       v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
     }
+  }
+  // Codes of this block and the N bits of this block and the next (one
+  // 128-byte mask line for 1024 bases, read once): the second half goes to
+  // `next` for the following block.  Whole pair inside the sequence, mask
+  // present.
+  __device__ __forceinline__ void load_pair_first(const ScanArgs& a, uint64_t base, uint32_t (&next)[MW]) {
+    load_codes(a, base);
+    const uint4* ms = reinterpret_cast<const uint4*>(a.nmask + (base >> 3));
+#pragma unroll
+    for (int i = 0; i < MW / 4; ++i) {
+      uint4 t = ms[i];
+      m[4 * i] = t.x; m[4 * i + 1] = t.y; m[4 * i + 2] = t.z; m[4 * i + 3] = t.w;
+      uint4 u = ms[MW / 4 + i];
+      next[4 * i] = u.x; next[4 * i + 1] = u.y; next[4 * i + 2] = u.z; next[4 * i + 3] = u.w;
+    }
+  }
+  __device__ __forceinline__ void load_second(const ScanArgs& a, uint64_t base, const uint32_t (&mask)[MW]) {
+    load_codes(a, base);
+#pragma unroll
+    for (int i = 0; i < MW; ++i) m[i] = mask[i];
+  }
+  // whole block inside the sequence
+  __device__ __forceinline__ void load(const ScanArgs& a, uint64_t base) {
+    load_codes(a, base);
     if (a.nmask) {
       const uint4* ms = reinterpret_cast<const uint4*>(a.nmask + (base >> 3));
 #pragma unroll
@@ -722,6 +745,19 @@ __device__ __forceinline__ uint32_t scan_blocks(const ScanArgs& a, const Tab& tb
   base += B::BASES;
   for (; base + B::BASES <= hi; base += B::BASES) {
     B cur;
+    if constexpr (ENC == ENC_2BIT) {
+      // two blocks under one 128-byte line of N bits: the line is read once
+      if ((base & (2 * B::BASES - 1)) == 0 && base + 2 * B::BASES <= hi && a.nmask) {
+        uint32_t next_mask[B::MW];
+        cur.load_pair_first(a, base, next_mask);
+        s = run_block<ENC, SHIFT, STEP, false>(tb, s, cur, base, base, base + B::BASES, sink);
+        base += B::BASES;
+        B nx;
+        nx.load_second(a, base, next_mask);
+        s = run_block<ENC, SHIFT, STEP, false>(tb, s, nx, base, base, base + B::BASES, sink);
+        continue;
+      }
+    }
     cur.load(a, base);
     s = run_block<ENC, SHIFT, STEP, false>(tb, s, cur, base, base, base + B::BASES, sink);
   }
