@@ -463,6 +463,8 @@ def main():
                     help="symbols per table lookup in the chunk scan (0 = the planner's choice; 1, 2 or 3)")
     ap.add_argument("--chunk", type=int, default=0, help="bases per chunk (0 = the workload's or the planner's)")
     ap.add_argument("--chains", type=int, default=0, help="chunks walked per lane at once (0 = the planner's choice)")
+    ap.add_argument("--lookback", type=int, default=0, help="bases before a chunk that narrow its starting states (0 = planner)")
+    ap.add_argument("--width", type=int, default=0, help="lanes per chunk in the speculation (0 = planner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -514,9 +516,11 @@ def main():
         if part is not None:
             part.count(seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains)
             return
-        coex.count(dfa, seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains)
+        coex.count(dfa, seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains,
+                   lookback=args.lookback, width=args.width)
         if w["find"]:
-            coex.find(dfa, seq, chunk=chunk, step=args.step, chains=args.chains)
+            coex.find(dfa, seq, chunk=chunk, step=args.step, chains=args.chains, lookback=args.lookback,
+                      width=args.width)
 
     # untimed: bring the GPU to its sustained clocks (about half a second of
     # steps), then the W warm-up steps of the contract
