@@ -460,7 +460,7 @@ struct DeviceCopy {
   size_t bytes = 0;
   uint32_t shift = 6;
   bool t2_exact = true;
-  bool dense = false;  // accepting states are visited in many three-symbol steps (see match_density)
+  bool dense = false;  // accepting states are visited in many three-symbol steps (Dfa::match_density)
   // per encoding [0] = byte, [1] = 2-bit
   const uint32_t* T2[2] = {nullptr, nullptr};
   const uint16_t* T3[2] = {nullptr, nullptr};  // automata of at most kMaxStatesStep3 states
@@ -518,26 +518,6 @@ const int kOrdByte[4] = {0, 1, 3, 2};  // A C T G ((byte >> 1) & 3)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Fraction of three-symbol steps that visit an accepting state, on a fixed
-// pseudo-random sequence of 3 * 8192 symbols run from q0.  Three symbols per
-// lookup pay a base-by-base replay for every 48-base unit holding a match, so
-// automata that match often (more than one step in 16) walk two symbols per
-// lookup, whose entries carry exact counts.
-double match_density(const Dfa& d) {
-  uint32_t s = d.q0, x = 12345u, hits = 0;
-  constexpr uint32_t kSteps = 8192;
-  for (uint32_t i = 0; i < kSteps; ++i) {
-    bool hit = false;
-    for (int j = 0; j < 3; ++j) {
-      x = x * 1664525u + 1013904223u;  // LCG (Numerical Recipes constants)
-      s = d.delta[s * 4 + (x >> 30)];
-      hit |= d.acc_index[s] >= 0;
-    }
-    hits += hit ? 1u : 0u;
-  }
-  return (double)hits / kSteps;
-}
-
 int upload(Dfa& d, int dev, DeviceCopy*& out) {
   std::lock_guard<std::mutex> lk(d.mu);
   if ((int)d.dev.size() > dev && d.dev[dev]) { out = d.dev[dev]; return COEX_OK; }
@@ -546,7 +526,7 @@ int upload(Dfa& d, int dev, DeviceCopy*& out) {
   dc->device = dev;
   dc->shift = n <= kMaxStatesStep2 ? 6 : 4;
   dc->t2_exact = d.max_out <= 15;
-  dc->dense = match_density(d) > 1.0 / 16;
+  dc->dense = d.match_density > kDenseMatches;
   const uint32_t S = dc->shift;
   std::vector<uint32_t> w(d.n_accepting);
   for (uint32_t i = 0; i < d.n_accepting; ++i) {

@@ -575,6 +575,22 @@ void analyze(Dfa& d) {
   }
   d.n_accepting = (uint32_t)d.acc_state.size();
   d.sync_depth = sync_depth(d);
+  {
+    // 3 * 8192 symbols of a linear congruential generator (Numerical
+    // Recipes constants, top two bits), run from q0
+    uint32_t s = d.q0, x = 12345u, hits = 0;
+    constexpr uint32_t kSteps = 8192;
+    for (uint32_t i = 0; i < kSteps; ++i) {
+      bool hit = false;
+      for (int j = 0; j < 3; ++j) {
+        x = x * 1664525u + 1013904223u;
+        s = d.delta[s * 4 + (x >> 30)];
+        hit |= d.acc_index[s] >= 0;
+      }
+      hits += hit ? 1u : 0u;
+    }
+    d.match_density = (double)hits / kSteps;
+  }
   // possible starting states after a k-base lookback: image of Q under the
   // k-gram, sorted; built level by level (append the newest symbol)
   std::vector<std::vector<uint16_t>> prev(1);

@@ -18,6 +18,13 @@ constexpr uint32_t kMaxStatesStep2 = 1024; // two-symbol table rows are 64 B
 constexpr uint32_t kMaxStatesStep3 = 1023; // three-symbol entries hold row * 64 + flag in 16 bits
 constexpr uint32_t kMaxLookback = 8;
 constexpr uint32_t kNoSync = 0xFFFFFFFFu;
+// match_density above which three symbols per lookup lose: a flagged 48-base
+// unit is replayed base by base (about 48 dependent lookups instead of 16),
+// so with d the fraction of flagged three-symbol steps a unit is replayed
+// with probability 1 - (1 - d)^16, and above d = 0.01 (16% of units) the
+// replays cost more than the 8 lookups per unit that two symbols per lookup
+// (exact counts, no replay) would add
+constexpr double kDenseMatches = 0.01;
 
 struct PssTable {              // possible starting states after a k-base lookback
   uint32_t k = 0;
@@ -40,6 +47,11 @@ struct Dfa {
   uint32_t n_accepting = 0;
   uint32_t max_out = 0;
   uint32_t sync_depth = kNoSync;
+  // three-symbol steps that visit an accepting state, as a fraction, on a
+  // fixed pseudo-random sequence run from q0 (walks of three symbols per
+  // lookup replay every 48-base unit that holds a match, so automata that
+  // match often walk two symbols per lookup, whose entries count exactly)
+  double match_density = 0.0;
   std::vector<int32_t> acc_index;  // state -> dense accepting index, -1 if not final
   std::vector<uint32_t> acc_state; // dense index -> state
   PssTable pss[kMaxLookback + 1];  // [1..8]
