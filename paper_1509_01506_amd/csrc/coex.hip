@@ -813,7 +813,10 @@ int make_plan(const Dfa& d, const DeviceCopy& dc, const coex_seq& sq, const coex
 
 }  // namespace
 
-int tail_block(const TailKey& k) { return (k.step == 3 && k.chains == 1) ? 1024 : kScanBlock; }
+int tail_block(const TailKey& k) {
+  if (k.chains == 2) return k.step == 3 ? TailShape<3, 2>::kBlock : TailShape<2, 2>::kBlock;
+  return k.step == 3 ? TailShape<3, 1>::kBlock : (k.step == 2 ? TailShape<2, 1>::kBlock : TailShape<1, 1>::kBlock);
+}
 
 int tail_occupancy(const TailKey& k, uint32_t lds) {
   if (k.enc == ENC_BYTE)

@@ -461,17 +461,17 @@ bool tail_dispatch(const TailKey& k, F&& f) {
   if (k.shift == 6) {
     if (k.step == 3) {
       if constexpr (MODE != MODE_POS)
-        if (k.chains == 2) return f(k_tail<ENC, 6, 3, MODE, 2>, 768);
-      return f(k_tail<ENC, 6, 3, MODE, 1>, 1024);
+        if (k.chains == 2) return f(k_tail<ENC, 6, 3, MODE, 2>, TailShape<3, 2>::kBlock);
+      return f(k_tail<ENC, 6, 3, MODE, 1>, TailShape<3, 1>::kBlock);
     }
     if (k.step == 2) {
       if constexpr (MODE != MODE_POS)
-        if (k.chains == 2) return f(k_tail<ENC, 6, 2, MODE, 2>, 768);
-      return f(k_tail<ENC, 6, 2, MODE, 1>, 768);
+        if (k.chains == 2) return f(k_tail<ENC, 6, 2, MODE, 2>, TailShape<2, 2>::kBlock);
+      return f(k_tail<ENC, 6, 2, MODE, 1>, TailShape<2, 1>::kBlock);
     }
-    return k.chains == 1 && f(k_tail<ENC, 6, 1, MODE, 1>, 768);
+    return k.chains == 1 && f(k_tail<ENC, 6, 1, MODE, 1>, TailShape<1, 1>::kBlock);
   }
-  return k.shift == 4 && k.step == 1 && k.chains == 1 && f(k_tail<ENC, 4, 1, MODE, 1>, 768);
+  return k.shift == 4 && k.step == 1 && k.chains == 1 && f(k_tail<ENC, 4, 1, MODE, 1>, TailShape<1, 1>::kBlock);
 }
 
 template <int ENC, int MODE>
