@@ -470,8 +470,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build scans one GPU's share; the multi-GPU sharding "
-              "(one boundary-state exchange and one count reduction) is described in DESIGN.md",
+        print("bench.py runs on one GPU only: the library scans one GPU's share of a sequence; sharding over "
+              "several GPUs (one exchange of boundary states, one reduction of counts) is not part of it",
               file=sys.stderr)
         sys.exit(2)
 
