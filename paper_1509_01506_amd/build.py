@@ -81,11 +81,11 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
         if errs:
             raise RuntimeError("compile failed:\n" + "\n".join(errs))
         rocm_lib = "/opt/rocm/lib"
-        _run(["g++", "-shared", "-pthread", "-o", tmp] + obj_dev + [obj_host, obj_serve, obj_hm, "-L" + rocm_lib,
+        _run(["g++", "-shared", "-pthread", "-o", tmp] + obj_dev + [obj_host, obj_serve, obj_hm, obj_fa, "-L" + rocm_lib,
               "-lamdhip64", "-Wl,-rpath," + rocm_lib], verbose)
         os.replace(tmp, out)
     finally:
-        for f in [obj_host, obj_serve, obj_hm, tmp] + obj_dev:
+        for f in [obj_host, obj_serve, obj_hm, obj_fa, tmp] + obj_dev:
             if os.path.exists(f):
                 os.remove(f)
     return out
