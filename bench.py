@@ -516,11 +516,13 @@ def main():
         if part is not None:
             part.count(seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains)
             return
+        if w["find"]:
+            # counts and end positions from one scan
+            coex.count_find(dfa, seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains,
+                            lookback=args.lookback, width=args.width)
+            return
         coex.count(dfa, seq, out=out, chunk=chunk, step=args.step, timed=timed, chains=args.chains,
                    lookback=args.lookback, width=args.width)
-        if w["find"]:
-            coex.find(dfa, seq, chunk=chunk, step=args.step, chains=args.chains, lookback=args.lookback,
-                      width=args.width)
 
     # untimed: bring the GPU to its sustained clocks (about half a second of
     # steps), then the W warm-up steps of the contract

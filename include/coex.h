@@ -213,6 +213,17 @@ int coex_count_noalloc(const coex_dfa* dfa, const coex_seq* seq, uint64_t* count
 int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32_t* pattern_dev,
               uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream);
 
+/* Counts and end positions from one scan (both results of "count and
+   extract", Section III.A): coex_find, then counts_dev uint64[n_patterns]
+   (device, caller-owned) from the matches found, one small kernel that
+   reads the pattern ids back (one-pattern automata: the number of matches).
+   The counts equal coex_count's.  pattern_dev is required when the
+   automaton has several patterns and capacity > 0 (else EINVAL).  On
+   ECAPACITY nothing is written to counts_dev and *n_found holds the
+   required size.  Errors: as for coex_find. */
+int coex_count_find(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, int64_t* pos_dev,
+                    uint32_t* pattern_dev, uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream);
+
 /* The per-chunk records of Algorithm 1 (CR: init state, last state, counts
    per pattern) for the true starting state of each chunk, for chunks of
    `chunk` bases (the last chunk takes the remainder).  n_chunks =

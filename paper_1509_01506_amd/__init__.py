@@ -29,7 +29,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EALPHABET", -3: "ETOOBIG", -4: "ENOMEM", -
 
 EXPORTED = ["coex_compile_kmers", "coex_compile_regex", "coex_dfa_from_table", "coex_dfa_info",
             "coex_dfa_export", "coex_dfa_free", "coex_count", "coex_count_noalloc", "coex_find",
-            "coex_count_chunks", "coex_count_host", "coex_errors_async", "coex_fasta_measure", "coex_fasta_read",
+            "coex_count_chunks", "coex_count_host", "coex_errors_async", "coex_count_find", "coex_fasta_measure", "coex_fasta_read",
             "coex_partition_kmers", "coex_partition_info", "coex_partition_part", "coex_count_partitioned",
             "coex_partition_free",
             "coex_count_batched", "coex_dfa_set_create", "coex_dfa_set_free", "coex_batch_create",
@@ -113,6 +113,7 @@ def _lib():
         L.coex_count.argtypes = [p, p, p, p, p]
         L.coex_count_noalloc.argtypes = [p, p, p, p, p]
         L.coex_errors_async.argtypes = [p, p]
+        L.coex_count_find.argtypes = [p, p, p, p, p, u64, p, p, p]
         L.coex_fasta_measure.argtypes = [p, u64, u32, u32, p, p]
         L.coex_partition_kmers.argtypes = [p, u32, u32, p]
         L.coex_partition_info.argtypes = [p, p, p]
@@ -457,6 +458,33 @@ def find(dfa: Dfa, seq: DeviceSeq, capacity: Optional[int] = None, chunk: int = 
     _check(rc, "find")
     m = int(n_found.value)
     return pos[:m], pat[:m]
+
+
+def count_find(dfa: Dfa, seq: DeviceSeq, out=None, capacity: Optional[int] = None, chunk: int = 0, width: int = 0,
+               lookback: int = 0, step: int = 0, timed: bool = False, stream=None, chains: int = 0):
+    """Counts and end positions from one scan (coex_count_find): (per-pattern
+    counts int64, end positions int64, pattern ids int32) CUDA tensors."""
+    import torch
+    dev = seq.bases.device
+    P = dfa.info().n_patterns
+    if out is None:
+        out = torch.empty(max(1, P), dtype=torch.int64, device=dev)
+    s = seq._c()
+    o = _opts(chunk, width, lookback, step, timed=timed, chains=chains)
+    n_found = ctypes.c_uint64(0)
+    cap = min(int(seq.n) * max(1, dfa.info().max_out), 1 << 20) if capacity is None else int(capacity)
+    for attempt in range(2):
+        pos = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
+        pat = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+        rc = _lib().coex_count_find(dfa.handle, ctypes.byref(s), out.data_ptr(), pos.data_ptr(), pat.data_ptr(), cap,
+                                    ctypes.byref(n_found), ctypes.byref(o), _stream(stream))
+        if rc == -5 and capacity is None and attempt == 0:
+            cap = int(n_found.value)
+            continue
+        break
+    _check(rc, "count_find")
+    m = int(n_found.value)
+    return out[:P], pos[:m], pat[:m]
 
 
 def count_host(dfa: Dfa, data: np.ndarray, n: Optional[int] = None, encoding: int = ENC_BYTE,

@@ -47,6 +47,7 @@ constexpr uint32_t kSmallSortKeys = 4096;
 size_t sort_temp_bytes(uint64_t cap);
 int sort_match_keys(const uint64_t* keys, uint64_t* tmp, uint64_t n, void* temp, size_t temp_bytes, int64_t* pos,
                     uint32_t* pat, uint64_t first, hipStream_t st);
+int counts_from_ids(const uint32_t* ids, uint64_t n, uint32_t n_pat, uint64_t* counts, hipStream_t st);
 
 // ====================================================================== kernels
 // The kept failure words of a stream's calls and of the no-allocation calls,
@@ -1414,6 +1415,26 @@ int coex_find(const coex_dfa* dfa, const coex_seq* seq, int64_t* pos_dev, uint32
     const bool one_pass = d.n_patterns <= (1u << 24) && seq->n_bases < (1ull << 40) - 256 && (!opts || opts->chains <= 1);
     return one_pass ? coex::find_one_pass(dfa, seq, pos_dev, pattern_dev, capacity, n_found, opts, stream)
                     : coex::find_two_pass(dfa, seq, pos_dev, pattern_dev, capacity, n_found, opts, stream);
+  } catch (const std::bad_alloc&) {
+    return COEX_ENOMEM;
+  } catch (...) {
+    return COEX_EINTERNAL;
+  }
+}
+
+int coex_count_find(const coex_dfa* dfa, const coex_seq* seq, uint64_t* counts_dev, int64_t* pos_dev,
+                    uint32_t* pattern_dev, uint64_t capacity, uint64_t* n_found, const coex_opts* opts, void* stream) {
+  if (!dfa || !counts_dev) return COEX_EINVAL;
+  try {
+    const Dfa& d = *reinterpret_cast<const Dfa*>(dfa);
+    if (d.n_patterns > 1 && capacity && !pattern_dev) return COEX_EINVAL;
+    const int rc = coex_find(dfa, seq, pos_dev, pattern_dev, capacity, n_found, opts, stream);
+    if (rc) return rc;
+    // several patterns and no id buffer: capacity 0, so no match was found
+    if (coex::counts_from_ids(d.n_patterns > 1 ? pattern_dev : nullptr, *n_found, d.n_patterns, counts_dev,
+                              (hipStream_t)stream))
+      return COEX_EDEVICE;
+    return COEX_OK;
   } catch (const std::bad_alloc&) {
     return COEX_ENOMEM;
   } catch (...) {

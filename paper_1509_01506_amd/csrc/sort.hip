@@ -52,6 +52,52 @@ __global__ void k_split_keys(const uint64_t* keys, uint64_t n, int64_t* pos, uin
   }
 }
 
+// Per-pattern counts of n matches from their pattern ids: per-block LDS
+// histograms added to the zeroed counts (n_pat <= kIdHist), else global
+// atomics.  ids NULL: a one-pattern automaton, every match is pattern 0.
+constexpr uint32_t kIdHist = 4096;
+
+__global__ void k_zero_counts(uint64_t* counts, uint32_t n_pat) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pat; i += gridDim.x * blockDim.x) counts[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_count_ids(const uint32_t* ids, uint64_t n, uint32_t n_pat,
+                                                   uint64_t* counts) {
+  __shared__ uint32_t h[kIdHist];
+  if (!ids) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[0] = n;
+    return;
+  }
+  const bool local = n_pat <= kIdHist;
+  if (local) {
+    for (uint32_t i = threadIdx.x; i < n_pat; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t id = ids[i];
+    if (id >= n_pat) continue;  // never: ids come from the automaton's output sets
+    if (local) atomicAdd(h + id, 1u);
+    else atomicAdd(reinterpret_cast<unsigned long long*>(counts + id), 1ull);
+  }
+  if (local) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_pat; i += blockDim.x)
+      if (h[i]) atomicAdd(reinterpret_cast<unsigned long long*>(counts + i), (unsigned long long)h[i]);
+  }
+}
+
+// counts_dev[0..n_pat) from the n pattern ids of a find (ids NULL: one
+// pattern, or no match at all).  Asynchronous.
+int counts_from_ids(const uint32_t* ids, uint64_t n, uint32_t n_pat, uint64_t* counts, hipStream_t st) {
+  if (n_pat == 0) return 0;
+  if (ids || n_pat > 1) hipLaunchKernelGGL(k_zero_counts, dim3((n_pat + 255) / 256), dim3(256), 0, st, counts, n_pat);
+  if (!ids && n_pat > 1) return hipGetLastError() == hipSuccess ? 0 : -1;  // no ids kept: no match
+  const uint64_t want = (n + 255) / 256;
+  const uint32_t blocks = (uint32_t)(want == 0 ? 1 : (want < 1024 ? want : 1024));
+  hipLaunchKernelGGL(k_count_ids, dim3(ids ? blocks : 1u), dim3(256), 0, st, ids, n, n_pat, counts);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // Temporary bytes the radix sort needs for up to `cap` keys.
 size_t sort_temp_bytes(uint64_t cap) {
   if (cap <= kSmallSort) return 0;

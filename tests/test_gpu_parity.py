@@ -106,6 +106,35 @@ def test_positions_multi_pattern(coex):
     assert e.value.name == "ECAPACITY"
 
 
+def test_count_find(coex):
+    # counts and end positions from one scan equal the oracle's, for several
+    # patterns (counts from the pattern ids), one pattern (count = matches),
+    # no match at all, and a capacity too small
+    n = 100_000
+    seq = synth.markov_bytes(23, n, with_n=True)
+    cases = [["ACG", "CG", "G", "TTAGG", "AGG", "ACGT", "ACG"], ["GATTACA"], ["ACGTACGTACGTACGTACGT"],
+             synth.random_kmers(24, 200, 9)]
+    for pats in cases:
+        d = coex.Dfa.kmers(pats)
+        ec, epos, epat = oracle.count_kmers(pats, oracle.byte_seq(seq), positions=True)
+        for chunk in [0, 1000]:
+            for enc in ["byte", "2bit"]:
+                s = dev_bytes(coex, seq) if enc == "byte" else dev_2bit(coex, seq)[0]
+                say("count_find", pats[:2], len(pats), enc, chunk)
+                c, pos, pat = coex.count_find(d, s, chunk=chunk)
+                assert c.cpu().numpy().view(np.uint64).tolist() == ec.tolist()
+                assert pos.cpu().numpy().tolist() == epos.tolist()
+                assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
+    d = coex.Dfa.kmers(cases[0])
+    s = dev_bytes(coex, seq)
+    with pytest.raises(coex.CoexError) as e:
+        coex.count_find(d, s, capacity=3)
+    assert e.value.name == "ECAPACITY"
+    # an empty sequence: zero counts, no positions
+    c, pos, _ = coex.count_find(d, dev_bytes(coex, seq[:0]))
+    assert c.cpu().numpy().tolist() == [0] * len(cases[0]) and pos.numel() == 0
+
+
 def test_regex_mid_fraction(coex):
     n = configs.MID_N // 64
     seq, rx = configs.mid(n)
@@ -438,8 +467,13 @@ def test_full_small_and_mid(coex):
     seq, kmers = configs.small()
     d = coex.Dfa.kmers(kmers)
     s = dev_bytes(coex, seq)
-    assert gpu_counts(coex, d, s, chunk=configs.SMALL_CHUNK).tolist() == \
-        oracle.count_kmers(kmers, oracle.byte_seq(seq))[0].tolist()
+    ec, epos, epat = oracle.count_kmers(kmers, oracle.byte_seq(seq), positions=True)
+    assert gpu_counts(coex, d, s, chunk=configs.SMALL_CHUNK).tolist() == ec.tolist()
+    # the bench step: counts and positions from one scan
+    c, pos, pat = coex.count_find(d, s, chunk=configs.SMALL_CHUNK)
+    assert c.cpu().numpy().view(np.uint64).tolist() == ec.tolist()
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+    assert pat.cpu().numpy().astype(np.uint32).tolist() == epat.tolist()
     seq, rx = configs.mid()
     say("mid full", rx)
     d = coex.Dfa.regex(rx)
@@ -447,6 +481,9 @@ def test_full_small_and_mid(coex):
     m, epos = oracle.Regex(rx).scan(oracle.byte_seq(seq), positions=True)
     assert gpu_counts(coex, d, s).tolist() == [m]
     pos, _ = coex.find(d, s)
+    assert pos.cpu().numpy().tolist() == epos.tolist()
+    c, pos, _ = coex.count_find(d, s)
+    assert c.cpu().numpy().view(np.uint64).tolist() == [m]
     assert pos.cpu().numpy().tolist() == epos.tolist()
 
 
