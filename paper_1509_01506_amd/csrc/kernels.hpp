@@ -596,21 +596,40 @@ struct Block<ENC_BYTE> {
   static constexpr uint64_t BASES = 128;
   static constexpr int WORDS = 8;
   uint4 r[8];
+  // Columns: each byte's code sits in its bits 0-1; t | t >> 6 puts two
+  // bases' codes in bytes 0 and 2, byte permutes gather those, and one more
+  // shift-or and permute give four codes per byte.  Resets: the high bit of
+  // every byte that is not A/C/G/T (either case), found without a per-byte
+  // compare ((b & 0x7F) + 0x7F has its high bit set for b & 0x7F nonzero);
+  // the per-base bits are only spread out for a word that mixes bases and
+  // resets.
   __device__ __forceinline__ void word(int w, uint32_t& cols, uint32_t& rst) const {
     const uint32_t x[4] = {r[w].x, r[w].y, r[w].z, r[w].w};
-    cols = 0;
-    rst = 0;
+    uint32_t p[4], nz[4], any = 0u, all = 0x80808080u;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t t = (x[i] >> 1) & 0x03030303u;
       const uint32_t expect = __builtin_amdgcn_perm(0u, 0x47544341u, t);  // 'A','C','T','G' by t
       const uint32_t bad = (x[i] & 0xDFDFDFDFu) ^ expect;                 // nonzero byte: not ACGTacgt
-      const uint32_t u = t | (t >> 6);
-      cols |= ((u & 0xFu) | ((u >> 12) & 0xF0u)) << (8 * i);
-      uint32_t rb = 0;
+      nz[i] = (((bad & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | bad) & 0x80808080u;
+      any |= nz[i];
+      all &= nz[i];
+      p[i] = t | (t >> 6);
+    }
+    const uint32_t q01 = __builtin_amdgcn_perm(p[1], p[0], 0x06040200u);  // bytes 0, 2 of p0 then of p1
+    const uint32_t q23 = __builtin_amdgcn_perm(p[3], p[2], 0x06040200u);
+    cols = __builtin_amdgcn_perm(q23 | (q23 >> 4), q01 | (q01 >> 4), 0x06040200u);
+    if (any == 0u) {
+      rst = 0u;
+    } else if (all == 0x80808080u) {
+      rst = 0xFFFFu;
+    } else {
+      rst = 0u;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) rb |= (((bad >> (8 * j)) & 0xFFu) != 0u) << j;
-      rst |= rb << (4 * i);
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t v = nz[i];
+        rst |= (((v >> 7) & 1u) | ((v >> 14) & 2u) | ((v >> 21) & 4u) | ((v >> 28) & 8u)) << (4 * i);
+      }
     }
   }
   __device__ __forceinline__ uint32_t any_reset() const { return 1u; }  // checked per word
